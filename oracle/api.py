@@ -1,0 +1,108 @@
+"""The four boundary calls, written plainly on top of the oracle modules.
+
+Same names as the library boundary: kl_synthesize, st_solve, activation_map,
+mlmc_estimate.  A workload is a plain dict (see the seeded-input module for the
+keys); ``level`` indexes its list of grids.
+
+Test infrastructure only (see the package docstring).
+"""
+
+import numpy as np
+
+from . import kl, mlmc, qoi, spacetime
+from .grid import Grid
+
+
+def level_grid(wl, level):
+    return Grid(wl["levels"][level], wl["lengths"])
+
+
+def initial_state(wl, grid):
+    """u0 = 1 inside the closed ball |x - c| <= r, else 0."""
+    x = grid.nodes()
+    c = np.asarray(wl["ic_center"], dtype=np.float64)[: grid.dim]
+    r = wl["ic_radius"]
+    return (((x - c) ** 2).sum(axis=1) <= r * r).astype(np.float64)
+
+
+def level_problem(wl, level, **kw):
+    g = level_grid(wl, level)
+    args = dict(
+        grid=g, m=wl["steps"][level], T=wl["T"], u0=initial_state(wl, g),
+        k_react=wl["k_react"], a_react=wl["a_react"], sigma_f0=wl["sigma_f0"],
+        transverse_ratio=wl["transverse_ratio"], fiber_law=wl["fiber_law"],
+    )
+    args.update(kw)
+    return spacetime.STProblem(**args)
+
+
+def kl_basis(wl):
+    """Nystrom KL eigenpairs of the workload's covariance on its KL grid."""
+    g = Grid(wl["kl_grid"], wl["lengths"])
+    return kl.NystromKL(g, wl["ell"], wl["s2"], wl["n_modes"])
+
+
+def kl_modes(wl, level, basis=None):
+    """modes[e, k] = sqrt(lambda_k) phi_k(x_e) at the level's element centroids."""
+    basis = kl_basis(wl) if basis is None else basis
+    return basis.modes(level_grid(wl, level).centroids())
+
+
+def kl_synthesize(modes, xi, sigma_f0):
+    return kl.synthesize_sigma(modes, xi, sigma_f0)
+
+
+def st_solve(wl, level, sigma, u0_guess=None, mode="block", **kw):
+    """Solve every sample; returns (U (S, m, n), list of NewtonStats)."""
+    prob = level_problem(wl, level, **kw)
+    sigma = np.atleast_2d(sigma)
+    out = np.empty((sigma.shape[0], prob.m, prob.grid.n))
+    stats = []
+    for s in range(sigma.shape[0]):
+        guess = None if u0_guess is None else u0_guess[s]
+        out[s], st = spacetime.newton(prob, sigma[s], guess, mode=mode)
+        stats.append(st)
+    return out, stats
+
+
+def activation_map(wl, level, U):
+    """(t_act (S, n), n_censored per sample)."""
+    prob = level_problem(wl, level)
+    U = np.asarray(U)
+    if U.ndim == 2:
+        U = U[None]
+    t = np.empty((U.shape[0], prob.grid.n))
+    cens = []
+    for s in range(U.shape[0]):
+        t[s], c = qoi.activation_map(prob.u0, U[s], prob.dt, wl["threshold"])
+        cens.append(c)
+    return t, cens
+
+
+def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
+    """MLMC mean/variance of the activation map on the finest grid.
+
+    N[l] samples on level l; xi_levels[l] (N[l], M) are the inputs shared by
+    the fine (level l) and coarse (level l-1) member of each pair;
+    modes_levels[l] the KL modes at level l's element centroids.
+    """
+    L1 = len(N)
+    finest = level_grid(wl, L1 - 1)
+    weights = finest.lumped_weights()
+    fine_q, coarse_q = [], []
+
+    def level_qoi(lv, xi):
+        sig = kl_synthesize(modes_levels[lv], xi, wl["sigma_f0"])
+        U, _ = st_solve(wl, lv, sig, mode=solve_mode)
+        t, _ = activation_map(wl, lv, U)
+        g = level_grid(wl, lv)
+        return np.array([mlmc.interpolate(g, ti, finest) for ti in t])
+
+    for l in range(L1):
+        xi = np.asarray(xi_levels[l])[: N[l]]
+        fine_q.append(level_qoi(l, xi))
+        coarse_q.append(level_qoi(l - 1, xi) if l > 0 else None)
+    out = mlmc.mlmc_combine(fine_q, coarse_q, weights)
+    out["fine_q"] = fine_q
+    out["coarse_q"] = coarse_q
+    return out

@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs and workload descriptions shared by tests and bench.
+
+This module holds data only -- workload sizes, parameters and the seeded
+random draws of the KL coefficients -- and none of the method's arithmetic.
+Both the CPU oracle and the HIP library receive what it produces as plain
+arrays and numbers.
+
+Workloads (2D sizes count nodes per axis; 3D sizes count nodes per axis of a
+grid whose element counts are 64 x 64 x 16 etc.):
+
+  small_mc_2d   33^2 nodes, 64 steps, 16 KL modes, 32 samples, FP64, one level
+  mlmc3_2d      33^2/65^2/129^2 with 64/128/256 steps, 32 modes,
+                512/128/32 fine/coarse pairs, FP64 batched, warm start
+  mlmc4_2d_mixed  33^2 ... 257^2 with 64 ... 512 steps, 64 modes,
+                1024/256/64/16 pairs, mixed precision
+  slab3d        [0,1]^2 x [0,0.25], 65 x 65 x 17 nodes, 256 steps, 64 modes
+                (ell 0.15, s2 0.2), 256 samples, mixed precision
+  mlmc5_3d      five 3D levels 9x9x3 ... 129x129x33 nodes, 32 ... 512 steps,
+                128 modes, sample counts chosen adaptively
+"""
+
+import numpy as np
+
+DEFAULT_SEED = 1911
+
+_COMMON_2D = dict(
+    dim=2,
+    lengths=(1.0, 1.0),
+    T=1.0,
+    k_react=8.0,
+    a_react=0.1,
+    sigma_f0=1e-3,
+    transverse_ratio=0.1,
+    fiber_law="diag2d",
+    ic_center=(0.0, 0.0),
+    ic_radius=0.1,
+    threshold=0.5,
+    ell=0.2,
+    s2=0.1,
+    kl_grid=(41, 41),
+)
+
+_COMMON_3D = dict(
+    dim=3,
+    lengths=(1.0, 1.0, 0.25),
+    T=1.0,
+    k_react=8.0,
+    a_react=0.1,
+    sigma_f0=1e-3,
+    transverse_ratio=0.1,
+    fiber_law="rot3d",
+    ic_center=(0.0, 0.0, 0.0),
+    ic_radius=0.1,
+    threshold=0.5,
+    ell=0.15,
+    s2=0.2,
+    kl_grid=(21, 21, 6),
+)
+
+
+def _w(base, **kw):
+    d = dict(base)
+    d.update(kw)
+    return d
+
+
+WORKLOADS = {
+    "small_mc_2d": _w(_COMMON_2D, name="small_mc_2d", levels=[(33, 33)], steps=[64],
+                      n_modes=16, samples=[32], precision="fp64"),
+    "mlmc3_2d": _w(_COMMON_2D, name="mlmc3_2d", levels=[(33, 33), (65, 65), (129, 129)],
+                   steps=[64, 128, 256], n_modes=32, samples=[512, 128, 32],
+                   precision="fp64"),
+    "mlmc4_2d_mixed": _w(_COMMON_2D, name="mlmc4_2d_mixed",
+                         levels=[(33, 33), (65, 65), (129, 129), (257, 257)],
+                         steps=[64, 128, 256, 512], n_modes=64,
+                         samples=[1024, 256, 64, 16], precision="mixed"),
+    "slab3d": _w(_COMMON_3D, name="slab3d", levels=[(65, 65, 17)], steps=[256],
+                 n_modes=64, samples=[256], precision="mixed"),
+    "mlmc5_3d": _w(_COMMON_3D, name="mlmc5_3d",
+                   levels=[(9, 9, 3), (17, 17, 5), (33, 33, 9), (65, 65, 17), (129, 129, 33)],
+                   steps=[32, 64, 128, 256, 512], n_modes=128, samples=None,
+                   target_rmse=1e-3, pilot=32, precision="mixed"),
+}
+
+WORKLOAD_IDS = {name: i for i, name in enumerate(WORKLOADS)}
+
+
+def workload(name, **overrides):
+    """A copy of a workload description with optional overrides."""
+    w = dict(WORKLOADS[name])
+    w.update(overrides)
+    return w
+
+
+def xi(name, level, n_samples, n_modes, seed=DEFAULT_SEED, start=0):
+    """Standard normal KL coefficients (n_samples, n_modes) for one MLMC level.
+
+    One PCG64 stream per (seed, workload, level), drawn in sample order, so a
+    longer draw extends a shorter one (prefix stable): rows start .. start+n.
+    """
+    ss = np.random.SeedSequence([seed, WORKLOAD_IDS.get(name, 99), level])
+    g = np.random.Generator(np.random.PCG64(ss))
+    full = g.standard_normal((start + n_samples, n_modes))
+    return np.ascontiguousarray(full[start:])
+
+
+def uniform_field(n, seed, lo=0.0, hi=1.0):
+    """Seeded uniform values, e.g. test vectors or perturbed states."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7])))
+    return g.uniform(lo, hi, size=n)
+
+
+def normal_field(shape, seed):
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    return g.standard_normal(shape)
