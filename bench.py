@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark: one MLMC estimate of the activation-map mean and variance per step.
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+KL synthesis of every sample's conductivity (fine and coarse member of each
+pair), the nonlinear space-time solve of every sample, the activation maps,
+and the MLMC mean/variance accumulation.  Inputs (KL modes, KL coefficients)
+are resident on the GPU before the timed region.
+
+Prints one JSON line.  Default workload: the three-level float64 MLMC
+(33^2/65^2/129^2 grids, 64/128/256 steps, 512/128/32 pairs, 32 KL modes).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _oracle_worker(args):
+    """One oracle sample: KL field, space-time solve, activation map (CPU, FP64)."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    wl, level, modes, xi = args
+    import oracle.api as oapi
+    sig = oapi.kl_synthesize(modes, xi[None, :], wl["sigma_f0"])
+    t0 = time.perf_counter()
+    U, _ = oapi.st_solve(wl, level, sig)
+    oapi.activation_map(wl, level, U)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(wl, modes, N, total_dof_steps, budget_s):
+    """Time the oracle on a bounded sample of the workload's coarsest-level solves.
+
+    The rate is measured in solved dof*steps per second and converted to the
+    workload's MLMC samples per second (samples / total dof*steps of a step).
+    """
+    import multiprocessing as mp
+    import numpy as np
+    import stinputs
+    cores = max(1, min(16, os.cpu_count() or 1))
+    n = wl["levels"][0]
+    nodes = int(np.prod(n))
+    m = wl["steps"][0]
+    xi = stinputs.xi(wl["name"], 0, 64, wl["n_modes"])
+    # one probe sample fixes the count that fits the budget
+    t_one = _oracle_worker((wl, 0, modes[0], xi[0]))
+    per_core = max(1, int(budget_s / max(t_one, 1e-3) / cores))
+    count = min(64, per_core * cores)
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_worker, [(wl, 0, modes[0], xi[i % 64]) for i in range(count)])
+    wall = time.perf_counter() - t0
+    rate = count * nodes * m / wall
+    samples = float(sum(N))
+    return {
+        "value": rate * samples / total_dof_steps,
+        "unit": "MLMC samples/s (from oracle dof*steps/s)",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "%d level-0 solves (%s nodes x %d steps, KL + Newton/SuperLU + activation) on %d "
+                  "processes, %.1f s wall, %.1f s CPU; converted via the workload's %d samples / %.4g dof*steps"
+                  % (count, "x".join(map(str, n)), m, cores, wall, sum(times), int(samples), total_dof_steps),
+        "dof_steps_per_s": rate,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mlmc3_2d")
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--max-lanes", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0 = skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported" % args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import stinputs
+    from paper_1911_06066_amd import Context, klmodes
+
+    dev = torch.device("cuda:0")
+    wl = stinputs.workload(args.workload)
+    if args.precision:
+        wl["precision"] = args.precision
+    N = list(wl["samples"])
+    M = wl["n_modes"]
+    modes_h = klmodes.workload_modes(wl)
+    modes = [torch.from_numpy(m).to(dev) for m in modes_h]
+    xi = [torch.from_numpy(stinputs.xi(wl["name"], l, N[l], M)).to(dev) for l in range(len(N))]
+    over = {}
+    if args.max_lanes:
+        over["max_lanes"] = args.max_lanes
+    if args.block:
+        over["block_threads"] = args.block
+    ctx = Context(wl, **over)
+
+    for _ in range(args.warmup):
+        ctx.mlmc_estimate(N, modes, xi)
+    torch.cuda.synchronize()
+    solve_ms, solve_bytes = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.mlmc_estimate(N, modes, xi)
+        tm = ctx.timings()
+        solve_ms.append(tm["solve_ms"])
+        solve_bytes.append(tm["solve_bytes"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    samples = float(sum(N))
+    value = samples / (ms / 1e3)
+    dof_steps = float(out["dof_steps"])
+    achieved = float(np.mean(solve_bytes)) / (float(np.mean(solve_ms)) * 1e-3) / 1e9
+
+    line = {
+        "metric": "MLMC samples/sec & DOF*steps/s at fixed RMSE; stencil HBM GB/s vs peak",
+        "value": value,
+        "unit": "MLMC samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl["precision"] == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["name"],
+            "levels": [list(s) for s in wl["levels"]],
+            "time_steps": wl["steps"],
+            "samples_per_level": N,
+            "kl_modes": M,
+            "precision": wl["precision"],
+            "parallelism": "single GPU, one workgroup team per sample",
+        },
+        "dof_steps_per_s": dof_steps / (ms / 1e3),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "st_team_kernel",
+            "kernel_ms": float(np.mean(solve_ms)),
+        },
+        "detail": {
+            "kl_ms": tm["kl_ms"], "solve_ms": tm["solve_ms"], "stats_ms": tm["stats_ms"],
+            "teams": tm["solve_teams"], "block": tm["solve_block"],
+            "newton_iters": out["newton_iters"], "krylov_iters": out["krylov_iters"],
+            "algorithmic_bytes": out["algorithmic_bytes"], "censored_nodes": out["censored"],
+            "V": out["V"], "cost_s": out["cost"],
+        },
+    }
+    if args.cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline(wl, modes_h, N, dof_steps, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

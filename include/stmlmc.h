@@ -1,0 +1,237 @@
+/*
+ * stmlmc.h -- C interface of the space-time multilevel Monte Carlo library
+ * for the monodomain equation on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem ("Space-time
+ * multilevel Monte Carlo methods and their application to cardiac
+ * electrophysiology"): for every value of the random input, solve the
+ * nonlinear space-time system C u + r(u) = f (Sec. 3.3, eq. mono_disc) whose
+ * conductivity is a truncated Karhunen-Loeve expansion (Sec. 2.2,
+ * eq. KL-expansion), and combine the samples with the MC / MLMC estimators of
+ * Sec. 3.1.2 (eqs. MC-estimator, MLMC-estimator).
+ *
+ * Conventions shared by every call
+ *  - All bulk arrays are DEVICE pointers on the device that was current at
+ *    stm_create; the caller owns them; the library never frees caller memory.
+ *    Host pointers are named *_host or documented as host.
+ *  - Arrays are dense, row-major, float64 unless stated, with the layouts
+ *    given per argument.  Nodes are numbered x fastest, then y, then z;
+ *    elements likewise.  A space-time array u[s][k][i] stores time levels
+ *    k = 1..m (index k-1); the initial state is not stored.
+ *  - Work is enqueued on the stream given at stm_create.  Calls that return
+ *    host-side results (stats, counts, scalars) synchronise that stream.
+ *  - Every call returns an stm_status; none aborts or exits.  Argument errors
+ *    are detected before any work is enqueued (STM_E_INVALID).  HIP runtime
+ *    errors return STM_E_DEVICE.  The message of the last error of a context is
+ *    available from stm_last_error().
+ *  - One context per host thread; calls on one context are not thread safe.
+ */
+#ifndef STMLMC_H
+#define STMLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STM_OK = 0,
+  STM_E_INVALID = -1,        /* bad argument, shape or pointer */
+  STM_E_NOMEM = -2,          /* device workspace could not be allocated */
+  STM_E_DEVICE = -3,         /* HIP runtime error */
+  STM_E_NOT_CONVERGED = -4,  /* a Newton iteration hit its limit; results hold the last iterate */
+  STM_E_NONFINITE = -5,      /* NaN/Inf met in an input or a residual */
+  STM_E_UNSUPPORTED = -6     /* valid request this build does not handle */
+} stm_status;
+
+typedef enum {
+  STM_PREC_FP64 = 0,   /* every floating-point step in float64 */
+  STM_PREC_MIXED = 1   /* float32 Krylov/multigrid and split-fp16 KL GEMM inside float64 Newton refinement */
+} stm_precision;
+
+typedef enum {
+  STM_FIBER_DIAG2D = 0,  /* theta = pi/4 + 0.5 y */
+  STM_FIBER_ROT3D = 1,   /* theta = -pi/3 + (2 pi/3) z / lz */
+  STM_FIBER_X = 2,       /* theta = 0 */
+  STM_FIBER_DIAG = 3     /* theta = pi/4 */
+} stm_fiber_law;
+
+#define STM_MAX_LEVELS 8
+
+/* One MLMC level: nodes per axis (nz = 1 in 2D, all odd) and time steps. */
+typedef struct {
+  int nx, ny, nz;
+  int m;
+} stm_level;
+
+/*
+ * The problem: monodomain equation du/dt = div(D grad u) + f(u) on the box
+ * [0,lx] x [0,ly] (x [0,lz]) with homogeneous Neumann boundaries, backward
+ * Euler in time on [0,T], Q1 elements in space (Sec. 2.1, Sec. 3.2).
+ *   f(u) = k_react u (u - a_react)(1 - u)       (FitzHugh-Nagumo cubic, eq. ionic_term)
+ *   D_e  = sigma_e a a^T + transverse_ratio sigma_f0 (I - a a^T)
+ *   a    = (cos theta, sin theta[, 0]), theta from fiber_law at the element centroid
+ *   u(x, 0) = 1 in the closed ball |x - ic_center| <= ic_radius, else 0
+ * The activation map is the first time u reaches `threshold`.
+ */
+typedef struct {
+  int dim;                    /* 2 or 3 */
+  double lx, ly, lz;
+  double T;
+  double k_react, a_react;
+  double sigma_f0, transverse_ratio;
+  int fiber_law;              /* stm_fiber_law */
+  double ic_center[3], ic_radius;
+  double threshold;
+  int n_levels;               /* 1 .. STM_MAX_LEVELS, coarse to fine, each a 2:1 refinement */
+  stm_level levels[STM_MAX_LEVELS];
+  int n_modes;                /* KL modes M, 1 .. 256 */
+  int precision;              /* stm_precision */
+  /* solver controls; 0 selects the default */
+  double newton_tol;          /* max-norm Newton step per slab: 1e-12 (fp64), 1e-10 (mixed) */
+  int newton_max;             /* Newton iterations per slab: 30 */
+  double gmres_rtol;          /* relative Krylov residual: 1e-10 (fp64), 1e-5 (mixed) */
+  int gmres_restart;          /* Krylov dimension of one linear solve: 16, at most 30; an unfinished
+                                 solve is continued by the next Newton step */
+  int mg_levels;              /* multigrid grids of the V-cycle: 1 (smoothing on the level's grid only);
+                                 -1: as deep as the grid allows (coarsest >= 5 nodes per axis) */
+  int smooth_steps;           /* weighted-Jacobi sweeps before and after the coarse correction: 2 */
+  double smooth_omega;        /* fixed Jacobi weight (smoother 0): 0.7 */
+  int coarse_sweeps;          /* weighted-Jacobi sweeps on the coarsest grid (the only grid when
+                                 mg_levels = 1): 8, at most 32 */
+  int smoother;               /* 0 (default): sweep weights 1/xi_s, xi_s the Chebyshev roots on
+                                 [lmax/cheb_ratio, lmax] of D^-1 A, lmax by power iteration;
+                                 1: the fixed weight smooth_omega */
+  double cheb_ratio;          /* 10 (2D), 30 (3D) */
+  int lds_kb;                 /* LDS staging budget per workgroup in KiB: 64 */
+  int block_threads;          /* threads per workgroup: chosen from the grid size */
+  int max_lanes;              /* concurrent samples in flight per call: 1024 */
+} stm_problem;
+
+/* Per-sample solver statistics (host array filled by stm_st_solve). */
+typedef struct {
+  int status;                 /* stm_status of this sample */
+  int newton_max_per_slab;    /* largest Newton count of any time slab */
+  int64_t newton_iters;       /* Newton iterations summed over slabs */
+  int64_t krylov_iters;       /* Krylov iterations summed over all linear solves */
+  double final_step;          /* largest final max-norm Newton step over slabs */
+  double device_seconds;      /* wall time of this sample on its workgroup(s) */
+  double algorithmic_bytes;   /* bytes the solve's passes must move: each array a pass reads or
+                                 writes counted once per pass (cache re-reads not counted) */
+} stm_solve_stats;
+
+/* Device time of the last call's phases, measured with HIP events on the context stream. */
+typedef struct {
+  double kl_ms;               /* KL synthesis launches */
+  double solve_ms;            /* team-solver launches */
+  double stats_ms;            /* activation / MLMC statistics launches */
+  double solve_bytes;         /* algorithmic bytes of the solver launches (sum over samples) */
+  int solve_launches;
+  int solve_teams;            /* workgroups of the last solver launch */
+  int solve_block;            /* threads per workgroup of the last solver launch */
+} stm_timings;
+
+/* Output of stm_mlmc_estimate. Device arrays are caller-owned, n_L = nodes of the finest level. */
+typedef struct {
+  double* mean;               /* device [n_L]: MLMC mean of the activation map */
+  double* var;                /* device [n_L]: sum_l s^2(P Q_l) - s^2(P Q_{l-1}) */
+  double* level_mean;         /* device [(L+1) n_L] or NULL: mean of Y_l = P Q_l - P Q_{l-1} */
+  double* level_var;          /* device [(L+1) n_L] or NULL: unbiased variance of Y_l */
+  /* host-side outputs */
+  int N[STM_MAX_LEVELS];      /* samples used per level */
+  double V[STM_MAX_LEVELS];   /* |D|^-1 int s^2(Y_l) (lumped quadrature on the finest grid) */
+  double cost[STM_MAX_LEVELS];/* mean device seconds per sample pair of the level */
+  double bias_estimate;       /* |D|^-1/2 || mean(Y_L) ||_2 / (2^alpha - 1), alpha fitted (0 if L < 2) */
+  int64_t newton_iters;       /* over all samples */
+  int64_t krylov_iters;
+  int64_t censored;           /* nodes never activated, over all solved samples */
+  int rounds;                 /* allocation rounds (1 for fixed counts) */
+  int worst_status;
+  double algorithmic_bytes;   /* over all solves, as in stm_solve_stats */
+  int64_t dof_steps;          /* sum over solves of nodes x time steps (both pair members) */
+} stm_mlmc_result;
+
+typedef struct stm_ctx stm_ctx;
+
+/*
+ * Create a context for problem *p on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Validates the problem, builds the
+ * geometric-multigrid hierarchies of every level and the fibre tables.
+ * On error *out is NULL and the status says why.
+ */
+stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out);
+
+/* Release the context and its device workspace (synchronises its stream). */
+void stm_destroy(stm_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char* stm_last_error(const stm_ctx* ctx);
+
+/* Phase timings of the last kl/solve/activation/mlmc call on ctx (host output). */
+stm_status stm_get_timings(const stm_ctx* ctx, stm_timings* out);
+
+/* Nodes, elements and time steps of a level (host outputs, any may be NULL). */
+stm_status stm_level_size(const stm_ctx* ctx, int level, int* n_nodes, int* n_elements, int* m);
+
+/*
+ * KL synthesis (Sec. 2.2, eq. KL-expansion in lognormal form):
+ *   sigma[s][e] = sigma_f0 * exp( sum_k modes[e][k] * xi[s][k] ),
+ * modes[E][M] (the eigenfunctions at the element centroids of `level`, each
+ * column pre-scaled by sqrt(lambda_k)), xi[S][M], sigma[S][E]; E is the
+ * element count of the level and M = n_modes.  Computed as one matrix product
+ * on the matrix cores: float64 operands (STM_PREC_FP64) or split-fp16
+ * operands with float32 accumulation (STM_PREC_MIXED; relative error of the
+ * exponent about 1e-7).  S >= 0 (S = 0 is a no-op).
+ */
+stm_status stm_kl_synthesize(stm_ctx* ctx, int level, const double* modes, const double* xi,
+                             int S, double* sigma);
+
+/*
+ * Space-time solve of S samples on `level` (Sec. 3.3, eq. mono_disc, by
+ * Newton's method, Sec. 3.5): for each s, u[s] solves
+ *   M (u_k - u_{k-1}) / dt + K(sigma[s]) u_k - M f(u_k) = 0,  k = 1..m,
+ * with u_0 the initial state.  sigma[S][E] element conductivities,
+ * u[S][m][n] output.  u0_guess[S][m][n] (or NULL) is the initial Newton
+ * iterate; with NULL each workgroup lane starts from the solution of the
+ * previous sample it solved (the first from the initial state).
+ * stats_host[S] (or NULL) receives per-sample statistics and makes the call
+ * synchronous.  Returns the worst per-sample status.
+ */
+stm_status stm_st_solve(stm_ctx* ctx, int level, const double* sigma, const double* u0_guess,
+                        int S, double* u, stm_solve_stats* stats_host);
+
+/*
+ * Activation map of S space-time solutions u[S][m][n] on `level`:
+ * t_act[s][i] = 0 if u_0 >= threshold, else the first up-crossing of the
+ * threshold, linear in t between the bracketing time levels, else T
+ * (censored).  n_censored_host[S] (or NULL) receives the censored counts
+ * and makes the call synchronous.
+ */
+stm_status stm_activation_map(stm_ctx* ctx, int level, const double* u, int S, double* t_act,
+                              int* n_censored_host);
+
+/*
+ * MLMC estimate of the mean and variance of the activation map on the
+ * finest level (Sec. 3.1.2, eq. MLMC-estimator; single level = plain MC).
+ *   modes_host[l] : device pointer to modes of level l, [E_l][M]
+ *   xi_host[l]    : device pointer to [capacity_host[l]][M] KL coefficients
+ *                   of level l's sample pairs; pair i uses row i for both
+ *                   its fine (level l) and coarse (level l-1) member
+ *   N_host        : samples per level, or NULL for adaptive counts: pilot
+ *                   rounds of `pilot` samples, then N_l from the estimated
+ *                   V_l and cost per sample until the variance part of the
+ *                   mean-square error is below target_rmse^2 / 2, capped by
+ *                   capacity_host[l].
+ * Solutions stay on the device; only activation maps are kept and reduced
+ * (Welford per chunk of samples, merged in sample order).  Synchronous.
+ */
+stm_status stm_mlmc_estimate(stm_ctx* ctx, const int* N_host, const double* const* modes_host,
+                             const double* const* xi_host, const int* capacity_host,
+                             double target_rmse, int pilot, stm_mlmc_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STMLMC_H */

@@ -1,0 +1,190 @@
+// Activation map and MLMC statistics kernels (float64).
+//
+// Activation time of a node: 0 if the initial state is at or above the
+// threshold, else the first up-crossing in time located by linear
+// interpolation between the bracketing time levels, else T (censored).
+//
+// MLMC statistics (Sec. 3.1.2, eq. MLMC-estimator): each level's activation
+// maps are interpolated (nested Q1) to the finest grid; per finest node, the
+// samples of P Q_l, P Q_{l-1} and Y_l = P Q_l - P Q_{l-1} are reduced by
+// Welford updates over fixed chunks of samples and the chunk states merged in
+// chunk order (Chan et al.), so the result does not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "stm_launch.h"
+
+namespace stm {
+
+__global__ void activation_kernel(GridDev g, int dim, int m, double dt, double T, double thr, double cx, double cy,
+                                  double cz, double r2, const double* __restrict__ u, int S,
+                                  double* __restrict__ t_act, int* __restrict__ censored) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  int cen = 0;
+  if (i < g.n) {
+    const int ix = i % g.nx;
+    const int r = i / g.nx;
+    const int iy = (dim == 2) ? r : r % g.ny;
+    const int iz = (dim == 2) ? 0 : r / g.ny;
+    const double x = ix * g.hx - cx, y = iy * g.hy - cy, z = (dim == 3) ? iz * g.hz - cz : 0.0;
+    double prev = (x * x + y * y + z * z <= r2) ? 1.0 : 0.0;
+    double t = -1.0;
+    if (prev >= thr) {
+      t = 0.0;
+    } else {
+      const double* us = u + (int64_t)s * m * g.n + i;
+      for (int k = 0; k < m; ++k) {
+        const double cur = us[(int64_t)k * g.n];
+        if (cur >= thr) {
+          t = k * dt + dt * (thr - prev) / (cur - prev);
+          break;
+        }
+        prev = cur;
+      }
+    }
+    if (t < 0.0) {
+      t = T;
+      cen = 1;
+    }
+    t_act[(int64_t)s * g.n + i] = t;
+  }
+  // per-block count, then one integer atomic per block (exact)
+  __shared__ int sc[256];
+  sc[threadIdx.x] = cen;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sc[threadIdx.x] += sc[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && censored && sc[0]) atomicAdd(censored + s, sc[0]);
+}
+
+hipError_t launch_activation_map(const GridDev& g, int dim, int m, double dt, double T, double thr, double cx,
+                                 double cy, double cz, double r2, const double* u, int S, double* t_act,
+                                 int* censored_dev, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  dim3 grid((g.n + 255) / 256, S);
+  hipLaunchKernelGGL(activation_kernel, grid, dim3(256), 0, st, g, dim, m, dt, T, thr, cx, cy, cz, r2, u, S, t_act,
+                     censored_dev);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(double* p, double v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+// Q1 interpolation of a field on grid gc (nested in gL, ratio 2^r per axis) at finest node p.
+__device__ __forceinline__ double interp_nested(const GridDev& gc, const GridDev& gL, int dim, const double* f,
+                                                int p) {
+  const int rx = (gL.nx - 1) / (gc.nx - 1);
+  const int ry = (gL.ny - 1) / (gc.ny - 1);
+  const int rz = (dim == 3) ? (gL.nz - 1) / (gc.nz - 1) : 1;
+  const int ix = p % gL.nx;
+  const int r = p / gL.nx;
+  const int iy = (dim == 2) ? r : r % gL.ny;
+  const int iz = (dim == 2) ? 0 : r / gL.ny;
+  const int I = ix / rx, J = iy / ry, K = iz / rz;
+  const double fx = double(ix - I * rx) / rx, fy = double(iy - J * ry) / ry, fz = double(iz - K * rz) / rz;
+  double acc = 0.0;
+  for (int c = 0; c < (dim == 3 ? 2 : 1); ++c) {
+    const double wz = (dim == 3) ? (c ? fz : 1.0 - fz) : 1.0;
+    if (wz == 0.0) continue;
+    for (int b = 0; b < 2; ++b) {
+      const double wy = b ? fy : 1.0 - fy;
+      if (wy == 0.0) continue;
+      for (int a = 0; a < 2; ++a) {
+        const double wx = a ? fx : 1.0 - fx;
+        if (wx == 0.0) continue;
+        const int q = (dim == 3) ? (((K + c) * gc.ny + (J + b)) * gc.nx + (I + a)) : ((J + b) * gc.nx + (I + a));
+        acc += wx * wy * wz * f[q];
+      }
+    }
+  }
+  return acc;
+}
+
+// Pass 1: Welford over each chunk of samples. part[c][0..5][p]: mean_f, M2_f, mean_c, M2_c, mean_y, M2_y.
+__global__ void level_chunk_kernel(StatsLevelArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (p >= a.gL.n) return;
+  const int s0 = c * a.chunk, s1 = min(a.N, s0 + a.chunk);
+  double mf = 0, qf2 = 0, mc = 0, qc2 = 0, my = 0, qy2 = 0;
+  int cnt = 0;
+  for (int s = s0; s < s1; ++s) {
+    const double vf = interp_nested(a.gf, a.gL, a.dim, a.tf + (int64_t)s * a.gf.n, p);
+    const double vc = a.tc ? interp_nested(a.gc, a.gL, a.dim, a.tc + (int64_t)s * a.gc.n, p) : 0.0;
+    const double vy = vf - vc;
+    ++cnt;
+    double d = vf - mf; mf += d / cnt; qf2 += d * (vf - mf);
+    d = vc - mc; mc += d / cnt; qc2 += d * (vc - mc);
+    d = vy - my; my += d / cnt; qy2 += d * (vy - my);
+  }
+  const int64_t n = a.gL.n;
+  double* q = a.part + (int64_t)c * 6 * n + p;
+  q[0] = mf; q[n] = qf2; q[2 * n] = mc; q[3 * n] = qc2; q[4 * n] = my; q[5 * n] = qy2;
+}
+
+// Pass 2: merge the chunk states in order, accumulate the MLMC mean/variance,
+// write the level fields, and per-block partial sums of w_p s^2(Y_l)(p).
+__global__ void level_merge_kernel(StatsLevelArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = a.gL.n;
+  double contrib = 0.0;
+  if (p < a.gL.n) {
+    const int nch = (a.N + a.chunk - 1) / a.chunk;
+    double cnt = 0, mf = 0, qf2 = 0, mc = 0, qc2 = 0, my = 0, qy2 = 0;
+    for (int c = 0; c < nch; ++c) {
+      const double nb = (double)(min(a.N, (c + 1) * a.chunk) - c * a.chunk);
+      const double* q = a.part + (int64_t)c * 6 * n + p;
+      const double tot = cnt + nb;
+      double d = q[0] - mf; mf += d * nb / tot; qf2 += q[n] + d * d * cnt * nb / tot;
+      d = q[2 * n] - mc; mc += d * nb / tot; qc2 += q[3 * n] + d * d * cnt * nb / tot;
+      d = q[4 * n] - my; my += d * nb / tot; qy2 += q[5 * n] + d * d * cnt * nb / tot;
+      cnt = tot;
+    }
+    const double den = a.N > 1 ? 1.0 / (a.N - 1) : 0.0;
+    const double vf = qf2 * den, vc = qc2 * den, vy = qy2 * den;
+    a.mean[p] += my;
+    a.var[p] += vf - (a.tc ? vc : 0.0);
+    if (a.level_mean) a.level_mean[p] = my;
+    if (a.level_var) a.level_var[p] = vy;
+    // lumped (trapezoid) weight of the finest node
+    const int ix = p % a.gL.nx;
+    const int r = p / a.gL.nx;
+    const int iy = (a.dim == 2) ? r : r % a.gL.ny;
+    const int iz = (a.dim == 2) ? 0 : r / a.gL.ny;
+    double w = a.gL.hx * a.gL.hy * ((ix == 0 || ix == a.gL.nx - 1) ? 0.5 : 1.0) *
+               ((iy == 0 || iy == a.gL.ny - 1) ? 0.5 : 1.0);
+    if (a.dim == 3) w *= a.gL.hz * ((iz == 0 || iz == a.gL.nz - 1) ? 0.5 : 1.0);
+    contrib = w * vy;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = contrib;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.vpart[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_level_stats(const StatsLevelArgs& a, hipStream_t st) {
+  if (a.N <= 0) return hipErrorInvalidValue;
+  const int nch = (a.N + a.chunk - 1) / a.chunk;
+  dim3 g1((a.gL.n + 255) / 256, nch);
+  hipLaunchKernelGGL(level_chunk_kernel, g1, dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(level_merge_kernel, dim3((a.gL.n + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace stm

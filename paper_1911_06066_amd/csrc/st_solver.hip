@@ -1,0 +1,812 @@
+// Fused space-time solver: one workgroup (a "team") owns one sample at a time
+// and runs its whole nonlinear space-time solve without leaving the kernel.
+//
+// Method (Sec. 3.3 eq. mono_disc, Sec. 3.5): the backward-Euler space-time
+// system is block lower bidiagonal, so Newton's method on it can be carried
+// out slab by slab in time order (block forward substitution, eq. system_C):
+// slab k is iterated with Newton steps A_k delta = -R_k until its correction is
+// below tolerance, given the converged slab k-1.  Each linear step is GMRES,
+// right-preconditioned by one geometric-multigrid V-cycle with weighted-Jacobi
+// smoothing on the slab operator A_k = M/dt + K - M diag f'(u_k) (with one
+// grid the V-cycle reduces to its smoothing sweeps).  The Jacobi weights are
+// either fixed or the reciprocal Chebyshev roots of an interval
+// [lmax/ratio, lmax] of D^-1 A, lmax estimated by power iteration once per
+// sample.  The initial iterate of slab k takes the time increment of a
+// previous solution (u_{k-1} + W_k - W_{k-1}; the paper initialises Newton
+// from already computed samples) or, without one, u_{k-1}.  The activation
+// map is updated as each slab is accepted.
+//
+// Memory: stencil passes on the level's own grid stage tiles of their two
+// nodal input fields and of the element conductivities into LDS with
+// coalesced independent loads, then compute from LDS; coarse multigrid grids
+// are read from global memory.
+//
+// Precision: the residual R_k, the update u += delta, the activation
+// interpolation and every stored solution are float64.  The Krylov and
+// multigrid vectors use TI (double, or float for iterative refinement).
+#include "stm_device.h"
+#include "q1_stencil.h"
+#include "stm_launch.h"
+
+namespace stm {
+
+template <int DIM>
+__device__ __forceinline__ void decode(const GridDev& g, int idx, int& i, int& j, int& k) {
+  i = idx % g.nx;
+  const int r = idx / g.nx;
+  if constexpr (DIM == 2) {
+    j = r;
+    k = 0;
+  } else {
+    j = r % g.ny;
+    k = r / g.ny;
+  }
+}
+
+template <typename T, int DIM>
+struct TensorOf;
+template <typename T>
+struct TensorOf<T, 2> { using type = Tensor2<T>; };
+template <typename T>
+struct TensorOf<T, 3> { using type = Tensor3<T>; };
+
+// Element tensor from the fibre conductivity s and the fibre-row table entry f.
+template <typename T, int DIM>
+__device__ __forceinline__ typename TensorOf<T, DIM>::type tensor_from(double s, const double* __restrict__ f,
+                                                                       double tau) {
+  const double c2 = f[0], s2 = f[1], cs = f[2];
+  if constexpr (DIM == 2) {
+    return Tensor2<T>{T(s * c2 + tau * s2), T(s * s2 + tau * c2), T((s - tau) * cs)};
+  } else {
+    return Tensor3<T>{T(s * c2 + tau * s2), T(s * s2 + tau * c2), T(tau), T((s - tau) * cs)};
+  }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ typename TensorOf<T, DIM>::type tensor_stored(const T* __restrict__ D,
+                                                                         const GridDev& g, int ex, int ey,
+                                                                         int ez) {
+  const int e = (DIM == 2) ? (ey * g.ex + ex) : ((ez * g.ey + ey) * g.ex + ex);
+  if constexpr (DIM == 2) {
+    return Tensor2<T>{D[4 * e], D[4 * e + 1], D[4 * e + 3]};
+  } else {
+    return Tensor3<T>{D[4 * e], D[4 * e + 1], D[4 * e + 2], D[4 * e + 3]};
+  }
+}
+
+// y = M fm + K fk at node (i, j, k); accessors take coordinates.
+template <typename T, int DIM, typename FM, typename FK, typename FD>
+__device__ __forceinline__ T apply_at(const GridDev& g, int i, int j, int k, FM fm, FK fk, FD fd, T wself,
+                                      T* diag) {
+  if constexpr (DIM == 2) {
+    return q1_apply_2d<T>(g, i, j, [&](int a, int b) { return fm(a, b, 0); },
+                          [&](int a, int b) { return fk(a, b, 0); }, [&](int ex, int ey) { return fd(ex, ey, 0); },
+                          wself, diag);
+  } else {
+    return q1_apply_3d<T>(g, i, j, k, fm, fk, fd, wself, diag);
+  }
+}
+
+__device__ __forceinline__ double react(double u, double kr, double ar) { return kr * u * (u - ar) * (1.0 - u); }
+__device__ __forceinline__ double react_d(double u, double kr, double ar) {
+  return kr * (-3.0 * u * u + 2.0 * (1.0 + ar) * u - ar);
+}
+
+template <typename TI, int DIM, int BLOCK>
+struct Team {
+  const LevelDev* L;
+  SolverParams prm;
+  const double* sigma;
+  TI *V, *Z;
+  int64_t vstride;
+  unsigned char* work;
+  unsigned char* smem;   // dynamic LDS staging area
+  double* omega;         // shared: per grid, the sweep weights [kMaxMG][kMaxSweeps]
+  // Algorithmic bytes of the passes run so far: every array a pass reads or
+  // writes counted once per pass (neighbour and halo re-reads are cache/LDS
+  // traffic, not counted).  Uniform across the block; thread 0 reports it.
+  mutable double bytes;
+
+  __device__ __forceinline__ double dbytes(int l) const {
+    return l == 0 ? 8.0 * L->g[0].ne : 4.0 * sizeof(TI) * L->g[l].ne;
+  }
+  __device__ TI* mgX(int l) const { return l == 0 ? nullptr : reinterpret_cast<TI*>(work + L->off_mgX[l]); }
+  __device__ TI* mgT(int l) const { return reinterpret_cast<TI*>(work + L->off_mgT[l]); }
+  __device__ TI* mgB(int l) const { return reinterpret_cast<TI*>(work + L->off_mgB[l]); }
+  __device__ TI* mgW(int l) const { return reinterpret_cast<TI*>(work + L->off_mgW[l]); }
+  __device__ TI* mgD(int l) const { return reinterpret_cast<TI*>(work + L->off_mgD[l]); }
+
+  // ---- staged pass on grid 0 ----------------------------------------------
+  // Stages fields fa, fb (type T) and the element conductivities of each tile
+  // into LDS, then calls body(i, j, k, idx, A, B, S) for every node of the
+  // tile; A(ii, jj, kk), B(...) read the staged fields, S(ex, ey, ez) the
+  // element tensor.  Ends with a barrier.
+  template <typename T, typename Body>
+  __device__ void staged(const T* __restrict__ fa, const T* __restrict__ fb, Body body) const {
+    const GridDev& g = L->g[0];
+    const int nx = g.nx;
+    const int Ry = sizeof(T) == 8 ? L->tile_y8 : L->tile_y4;
+    const int Rz = (DIM == 3) ? (sizeof(T) == 8 ? L->tile_z8 : L->tile_z4) : 1;
+    const int nzz = (DIM == 3) ? g.nz : 1;
+    const double* __restrict__ sg = sigma;
+    const double* __restrict__ fib = L->fib;
+    const double tau = prm.tau;
+    for (int k0 = 0; k0 < nzz; k0 += Rz) {
+      for (int j0 = 0; j0 < g.ny; j0 += Ry) {
+        const int jr0 = max(j0 - 1, 0), jr1 = min(j0 + Ry, g.ny - 1);
+        const int kr0 = (DIM == 3) ? max(k0 - 1, 0) : 0, kr1 = (DIM == 3) ? min(k0 + Rz, g.nz - 1) : 0;
+        const int sy = jr1 - jr0 + 1;
+        const int nst = sy * (kr1 - kr0 + 1) * nx;
+        T* la = reinterpret_cast<T*>(smem);
+        T* lb = la + nst;
+        double* ls = reinterpret_cast<double*>(smem + ((2 * nst * sizeof(T) + 15) & ~(size_t)15));
+        for (int q = threadIdx.x; q < nst; q += BLOCK) {
+          const int i = q % nx, r = q / nx;
+          const int jj = jr0 + r % sy, kk = kr0 + r / sy;
+          const int gq = (DIM == 3) ? ((kk * g.ny + jj) * nx + i) : (jj * nx + i);
+          la[q] = fa[gq];
+          lb[q] = fb[gq];
+        }
+        const int ey0 = max(j0 - 1, 0), ey1 = min(j0 + Ry - 1, g.ey - 1);
+        const int ez0 = (DIM == 3) ? max(k0 - 1, 0) : 0, ez1 = (DIM == 3) ? min(k0 + Rz - 1, g.ez - 1) : 0;
+        const int sey = ey1 - ey0 + 1;
+        const int nse = sey * (ez1 - ez0 + 1) * g.ex;
+        for (int q = threadIdx.x; q < nse; q += BLOCK) {
+          const int ex = q % g.ex, r = q / g.ex;
+          const int ey = ey0 + r % sey, ez = ez0 + r / sey;
+          ls[q] = sg[(DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex)];
+        }
+        __syncthreads();
+        auto A = [&](int ii, int jj, int kk) { return la[((kk - kr0) * sy + (jj - jr0)) * nx + ii]; };
+        auto B = [&](int ii, int jj, int kk) { return lb[((kk - kr0) * sy + (jj - jr0)) * nx + ii]; };
+        auto S = [&](int ex, int ey, int ez) {
+          const double s = ls[((ez - ez0) * sey + (ey - ey0)) * g.ex + ex];
+          return tensor_from<T, DIM>(s, fib + 3 * ((DIM == 3) ? ez : ey), tau);
+        };
+        const int cy = min(j0 + Ry, g.ny) - j0, cz = min(k0 + Rz, nzz) - k0;
+        const int nc = cy * cz * nx;
+        for (int q = threadIdx.x; q < nc; q += BLOCK) {
+          const int i = q % nx, r = q / nx;
+          const int j = j0 + r % cy, k = k0 + r / cy;
+          const int idx = (DIM == 3) ? ((k * g.ny + j) * nx + i) : (j * nx + i);
+          body(i, j, k, idx, A, B, S);
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // y = A_l x at node idx of a coarse grid l >= 1 (global memory)
+  __device__ __forceinline__ TI apply_coarse(int l, const TI* __restrict__ x, int idx, TI* diag) const {
+    const GridDev& g = L->g[l];
+    const TI* __restrict__ w = mgW(l);
+    const TI* __restrict__ D = mgD(l);
+    int i, j, k;
+    decode<DIM>(g, idx, i, j, k);
+    auto flat = [&](int a, int b, int c) { return (DIM == 3) ? ((c * g.ny + b) * g.nx + a) : (b * g.nx + a); };
+    return apply_at<TI, DIM>(g, i, j, k, [&](int a, int b, int c) { const int q = flat(a, b, c); return w[q] * x[q]; },
+                             [&](int a, int b, int c) { return x[flat(a, b, c)]; },
+                             [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); }, w[idx],
+                             diag);
+  }
+
+  // diagonal of A_l at node idx (any grid; global memory)
+  __device__ __forceinline__ TI diag_at(int l, int idx) const {
+    const GridDev& g = L->g[l];
+    const TI* __restrict__ w = mgW(l);
+    int i, j, k;
+    decode<DIM>(g, idx, i, j, k);
+    TI d;
+    auto z = [&](int, int, int) { return TI(0); };
+    if (l == 0) {
+      const double* __restrict__ sg = sigma;
+      const double* __restrict__ fib = L->fib;
+      const double tau = prm.tau;
+      apply_at<TI, DIM>(g, i, j, k, z, z,
+                        [&](int ex, int ey, int ez) {
+                          const int e = (DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex);
+                          return tensor_from<TI, DIM>(sg[e], fib + 3 * ((DIM == 3) ? ez : ey), tau);
+                        },
+                        w[idx], &d);
+    } else {
+      const TI* __restrict__ D = mgD(l);
+      apply_at<TI, DIM>(g, i, j, k, z, z, [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); },
+                        w[idx], &d);
+    }
+    return d;
+  }
+
+  // ---- smoothing -----------------------------------------------------------
+  // out = x + om (b - A x) / diag ;  x == null means x = 0 (out = om b / diag)
+  __device__ void jacobi(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out,
+                         TI om) const {
+    const int n = L->g[l].n;
+    bytes += (x ? 4.0 : 3.0) * sizeof(TI) * n + dbytes(l);
+    if (!x) {
+      for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = om * b[idx] / diag_at(l, idx);
+      __syncthreads();
+      return;
+    }
+    if (l == 0) {
+      const TI* __restrict__ w = mgW(0);
+      staged<TI>(x, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
+        TI d;
+        const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
+                                        A, S, B(i, j, k), &d);
+        out[idx] = A(i, j, k) + om * (b[idx] - ax) / d;
+      });
+      return;
+    }
+    for (int idx = threadIdx.x; idx < n; idx += BLOCK) {
+      TI d;
+      const TI ax = apply_coarse(l, x, idx, &d);
+      out[idx] = x[idx] + om * (b[idx] - ax) / d;
+    }
+    __syncthreads();
+  }
+
+  __device__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
+    const int n = L->g[l].n;
+    bytes += 4.0 * sizeof(TI) * n + dbytes(l);
+    if (l == 0) {
+      const TI* __restrict__ w = mgW(0);
+      staged<TI>(x, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
+        const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
+                                        A, S, TI(0), (TI*)nullptr);
+        out[idx] = b[idx] - ax;
+      });
+      return;
+    }
+    for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = b[idx] - apply_coarse(l, x, idx, nullptr);
+    __syncthreads();
+  }
+
+  // coarse[l+1] = P^T fine[l]  (full weighting, transpose of Q1 interpolation)
+  __device__ void restrict_to(int l, const TI* __restrict__ rf, TI* __restrict__ bc) const {
+    const GridDev& gf = L->g[l];
+    const GridDev& gc = L->g[l + 1];
+    bytes += double(sizeof(TI)) * (gf.n + gc.n);
+    for (int idx = threadIdx.x; idx < gc.n; idx += BLOCK) {
+      int I, J, K;
+      decode<DIM>(gc, idx, I, J, K);
+      TI acc = TI(0);
+      const int kz0 = (DIM == 3) ? -1 : 0, kz1 = (DIM == 3) ? 1 : 0;
+      for (int c = kz0; c <= kz1; ++c) {
+        const int fk = 2 * K + c;
+        if (DIM == 3 && (fk < 0 || fk >= gf.nz)) continue;
+        const TI wz = (c == 0) ? TI(1) : TI(0.5);
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+          const int fj = 2 * J + b;
+          if (fj < 0 || fj >= gf.ny) continue;
+          const TI wy = (b == 0) ? TI(1) : TI(0.5);
+#pragma unroll
+          for (int a = -1; a <= 1; ++a) {
+            const int fi = 2 * I + a;
+            if (fi < 0 || fi >= gf.nx) continue;
+            const TI wx = (a == 0) ? TI(1) : TI(0.5);
+            acc += wx * wy * wz * rf[(DIM == 3 ? (fk * gf.ny + fj) : fj) * gf.nx + fi];
+          }
+        }
+      }
+      bc[idx] = acc;
+    }
+    __syncthreads();
+  }
+
+  // fine[l] += P coarse[l+1]  (Q1 interpolation of nested grids)
+  __device__ void prolong_add(int l, const TI* __restrict__ xc, TI* __restrict__ xf) const {
+    const GridDev& gf = L->g[l];
+    const GridDev& gc = L->g[l + 1];
+    bytes += double(sizeof(TI)) * (2.0 * gf.n + gc.n);
+    for (int idx = threadIdx.x; idx < gf.n; idx += BLOCK) {
+      int i, j, k;
+      decode<DIM>(gf, idx, i, j, k);
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int oi = i & 1, oj = j & 1, ok = (DIM == 3) ? (k & 1) : 0;
+      const TI w = (oi ? TI(0.5) : TI(1)) * (oj ? TI(0.5) : TI(1)) * (ok ? TI(0.5) : TI(1));
+      TI acc = TI(0);
+      for (int c = 0; c <= ok; ++c)
+        for (int b = 0; b <= oj; ++b)
+          for (int a = 0; a <= oi; ++a) {
+            const int q = (DIM == 3) ? (((K + c) * gc.ny + (J + b)) * gc.nx + (I + a)) : ((J + b) * gc.nx + (I + a));
+            acc += w * xc[q];
+          }
+      xf[idx] += acc;
+    }
+    __syncthreads();
+  }
+
+  // weight of sweep s (0-based) of grid l
+  __device__ __forceinline__ TI wgt(int l, int s) const {
+    if (prm.smoother == 0) return TI(prm.smooth_omega);
+    return TI(omega[l * kMaxSweeps + s]);
+  }
+
+  // out = V-cycle(b) on grid 0.  Sweep s of a level writes buf[(s-1) % 2];
+  // buf[1] is the level's output, so results land in place for any count.
+  __device__ void vcycle(const TI* __restrict__ b0, TI* __restrict__ out0) const {
+    const int nmg = L->nmg;
+    const int nu = prm.smooth_steps;
+    for (int l = 0; l < nmg - 1; ++l) {
+      TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
+      const TI* b = (l == 0) ? b0 : mgB(l);
+      jacobi(l, b, nullptr, buf[0], wgt(l, 0));
+      for (int s = 2; s <= nu; ++s) jacobi(l, b, buf[s % 2], buf[(s - 1) % 2], wgt(l, s - 1));
+      residual_inner(l, b, buf[(nu - 1) % 2], buf[nu % 2]);
+      restrict_to(l, buf[nu % 2], mgB(l + 1));
+    }
+    {
+      const int l = nmg - 1;
+      TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
+      const TI* b = (l == 0) ? b0 : mgB(l);
+      const int nc = prm.coarse_sweeps;
+      jacobi(l, b, nullptr, buf[0], wgt(l, 0));
+      for (int s = 2; s <= nc; ++s) jacobi(l, b, buf[s % 2], buf[(s - 1) % 2], wgt(l, s - 1));
+    }
+    for (int l = nmg - 2; l >= 0; --l) {
+      TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
+      const TI* b = (l == 0) ? b0 : mgB(l);
+      prolong_add(l, mgX(l + 1), buf[(nu - 1) % 2]);
+      for (int t = 1; t <= nu; ++t) jacobi(l, b, buf[(nu - 2 + t) % 2], buf[(nu - 1 + t) % 2], wgt(l, nu - t));
+    }
+  }
+
+  // lmax of D^-1 A_l by power iteration from a smooth + checkerboard start.
+  // Uses buffers x0, x1 of grid l.  Returns the estimate (block-uniform).
+  __device__ double power_lmax(int l, TI* x0, TI* x1, double* red) const {
+    const GridDev& g = L->g[l];
+    for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
+      int i, j, k;
+      decode<DIM>(g, idx, i, j, k);
+      x0[idx] = TI(1.0 + 0.5 * (((i + j + k) & 1) ? -1.0 : 1.0));
+    }
+    __syncthreads();
+    double lam = 0.0;
+    for (int it = 0; it < prm.power_iters; ++it) {
+      double nn[2] = {0.0, 0.0};
+      if (l == 0) {
+        const TI* __restrict__ w = mgW(0);
+        staged<TI>(x0, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
+          TI d;
+          const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
+                                          A, S, B(i, j, k), &d);
+          const TI y = ax / d;
+          x1[idx] = y;
+          nn[0] += double(y) * double(y);
+          nn[1] += double(A(i, j, k)) * double(A(i, j, k));
+        });
+      } else {
+        for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
+          TI d;
+          const TI ax = apply_coarse(l, x0, idx, &d);
+          const TI y = ax / d;
+          x1[idx] = y;
+          nn[0] += double(y) * double(y);
+          nn[1] += double(x0[idx]) * double(x0[idx]);
+        }
+      }
+      block_sum<BLOCK, 2>(nn, red);
+      lam = sqrt(nn[0] / nn[1]);
+      const TI scl = TI(1.0 / sqrt(nn[0]));
+      for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) x0[idx] = x1[idx] * scl;
+      __syncthreads();
+    }
+    bytes += prm.power_iters * (5.0 * sizeof(TI) * g.n + dbytes(l));
+    return lam;
+  }
+};
+
+// Weights 1 / xi_s, xi_s the roots of the degree-K Chebyshev polynomial
+// shifted to [a, b], ordered to alternate large and small roots.
+__device__ inline void chebyshev_weights(double a, double b, int K, double* w) {
+  const double th = 0.5 * (b + a), de = 0.5 * (b - a);
+  const double PI = 3.14159265358979323846;
+  for (int s = 0; s < K; ++s) {
+    const int r = (s % 2 == 0) ? s / 2 : K - 1 - s / 2;
+    const double xi = th + de * cos(PI * (2 * r + 1) / (2.0 * K));
+    w[s] = 1.0 / xi;
+  }
+}
+
+template <typename TI, int DIM, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restrict__ levels,
+                                                        const TeamTask* __restrict__ tasks, SolverParams prm) {
+  constexpr int NW = BLOCK / kWave;
+  extern __shared__ __align__(16) unsigned char smem_dyn[];
+  __shared__ double red[NW * 9];
+  __shared__ double H[(kMaxRestart + 1) * kMaxRestart];
+  __shared__ double cs_[kMaxRestart], sn_[kMaxRestart], gv[kMaxRestart + 1], sc[kMaxRestart + 1];
+  __shared__ double yv[kMaxRestart], coef[kMaxRestart + 1];
+  __shared__ double omega_tab[kMaxMG * kMaxSweeps];
+  __shared__ double sh_resid;
+
+  const TeamTask task = tasks[blockIdx.x];
+  const LevelDev* L = levels + task.level;
+  const int tid = threadIdx.x;
+
+  Team<TI, DIM, BLOCK> tm;
+  tm.L = L;
+  tm.prm = prm;
+  tm.work = task.work;
+  tm.smem = smem_dyn;
+  tm.omega = omega_tab;
+  tm.bytes = 0.0;
+  const GridDev g0 = L->g[0];
+  const int n0 = g0.n;
+  double* __restrict__ u = reinterpret_cast<double*>(task.work + L->off_u);
+  double* __restrict__ uprev = reinterpret_cast<double*>(task.work + L->off_uprev);
+  double* __restrict__ wk1 = reinterpret_cast<double*>(task.work + L->off_wk1);
+  double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
+  tm.V = reinterpret_cast<TI*>(task.work + L->off_V);
+  tm.Z = reinterpret_cast<TI*>(task.work + L->off_Z);
+  const int64_t vs = (int64_t)((n0 + 63) & ~63);
+  tm.vstride = vs;
+  double* ubuf = reinterpret_cast<double*>(task.work + L->off_U);
+
+  const int m = L->m;
+  const double dt = L->dt, inv_dt = 1.0 / L->dt;
+  const double kr = prm.k_react, ar = prm.a_react, tau = prm.tau, thr = prm.threshold;
+  const int restart = prm.restart;
+
+  bool have_prev = false;
+  const double* prevU = nullptr;
+
+  for (int it_s = 0; it_s < task.count; ++it_s) {
+    const int s = task.first + it_s * task.stride;
+    const long long t_start = wall_clock64();
+    tm.bytes = 0.0;
+    tm.sigma = task.sigma + (int64_t)s * g0.ne;
+    double* Uout = task.u_out ? task.u_out + (int64_t)s * m * n0 : ubuf;
+    const double* W = nullptr;
+    if (task.u_guess) W = task.u_guess + (int64_t)s * m * n0;
+    else if (have_prev) W = prevU;
+
+    // ---- per-sample setup: coarse element tensors (averages of children) ----
+    for (int l = 1; l < L->nmg; ++l) {
+      const GridDev& gc = L->g[l];
+      const GridDev& gf = L->g[l - 1];
+      TI* Dc = tm.mgD(l);
+      const TI* Df = tm.mgD(l - 1);
+      for (int e = tid; e < gc.ne; e += BLOCK) {
+        int E = e % gc.ex, F, G;
+        if constexpr (DIM == 2) {
+          F = e / gc.ex;
+          G = 0;
+        } else {
+          F = (e / gc.ex) % gc.ey;
+          G = e / (gc.ex * gc.ey);
+        }
+        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        const int cz = (DIM == 3) ? 2 : 1;
+        for (int c = 0; c < cz; ++c)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+              const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * G + c;
+              const int fe = (DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx);
+              if (l == 1) {
+                auto D = tensor_from<double, DIM>(tm.sigma[fe], L->fib + 3 * ((DIM == 3) ? fz : fy), tau);
+                a0 += D.xx;
+                a1 += D.yy;
+                a3 += D.xy;
+                if constexpr (DIM == 3) a2 += D.zz;
+              } else {
+                a0 += Df[4 * fe];
+                a1 += Df[4 * fe + 1];
+                a2 += Df[4 * fe + 2];
+                a3 += Df[4 * fe + 3];
+              }
+            }
+        const double inv = 1.0 / (4 * cz);
+        Dc[4 * e] = TI(a0 * inv);
+        Dc[4 * e + 1] = TI(a1 * inv);
+        Dc[4 * e + 2] = TI(a2 * inv);
+        Dc[4 * e + 3] = TI(a3 * inv);
+      }
+      __syncthreads();
+    }
+    // initial state, activation markers, warm-start history
+    for (int idx = tid; idx < n0; idx += BLOCK) {
+      int i, j, k;
+      decode<DIM>(g0, idx, i, j, k);
+      const double x = i * g0.hx - L->ic_cx, y = j * g0.hy - L->ic_cy, z = (DIM == 3) ? (k * g0.hz - L->ic_cz) : 0.0;
+      const double v = (x * x + y * y + z * z <= L->ic_r2) ? 1.0 : 0.0;
+      uprev[idx] = v;
+      wk1[idx] = v;
+      tact[idx] = (v >= thr) ? 0.0 : -1.0;
+    }
+    __syncthreads();
+
+    long long newton_total = 0, krylov_total = 0;
+    int newton_max_slab = 0, status = 0;
+    double worst_final = 0.0;
+    bool weights_ready = (prm.smoother == 0);
+
+    for (int k = 0; k < m; ++k) {
+      // ---- initial iterate of slab k ----
+      const double* Wk = W ? W + (int64_t)k * n0 : nullptr;
+      tm.bytes += (Wk ? 40.0 : 16.0) * n0;
+      for (int idx = tid; idx < n0; idx += BLOCK) {
+        if (Wk) {
+          const double w = Wk[idx];
+          u[idx] = uprev[idx] + (w - wk1[idx]);
+          wk1[idx] = w;
+        } else {
+          u[idx] = uprev[idx];
+        }
+      }
+      __syncthreads();
+
+      double dprev = 0.0, eta = fmax(prm.gmres_rtol, 1e-4);
+      int it = 0;
+      bool conv = false;
+      double dmax = 0.0;
+      for (; it < prm.newton_max; ++it) {
+        // ---- residual (float64) -> V_0, Jacobian weights on every grid ----
+        TI* V0 = tm.V;
+        TI* w0 = tm.mgW(0);
+        double rr[1] = {0.0};
+        tm.bytes += 16.0 * n0 + 8.0 * g0.ne + 2.0 * sizeof(TI) * n0;
+        for (int l = 1; l < L->nmg; ++l) tm.bytes += (8.0 + sizeof(TI)) * L->g[l].n;
+        tm.template staged<double>(u, uprev, [&](int i, int j, int kk, int idx, auto& A, auto& B, auto& S) {
+          const double y = apply_at<double, DIM>(
+              g0, i, j, kk,
+              [&](int a, int b, int c) {
+                const double uq = A(a, b, c);
+                return (uq - B(a, b, c)) * inv_dt - react(uq, kr, ar);
+              },
+              A, S, 0.0, (double*)nullptr);
+          const double r = -y;
+          V0[idx] = TI(r);
+          w0[idx] = TI(inv_dt - react_d(A(i, j, kk), kr, ar));
+          rr[0] += r * r;
+        });
+        for (int l = 1; l < L->nmg; ++l) {
+          const GridDev& gc = L->g[l];
+          TI* wl = tm.mgW(l);
+          const int st = 1 << l;
+          for (int idx = tid; idx < gc.n; idx += BLOCK) {
+            int I, J, K;
+            decode<DIM>(gc, idx, I, J, K);
+            const int q = (DIM == 3) ? (((K * st) * g0.ny + J * st) * g0.nx + I * st) : ((J * st) * g0.nx + I * st);
+            wl[idx] = TI(inv_dt - react_d(u[q], kr, ar));
+          }
+        }
+        block_sum<BLOCK, 1>(rr, red);  // its barriers also publish the writes above
+        const double beta = sqrt(rr[0]);
+        if (!isfinite(beta)) {
+          status = -5;
+          break;
+        }
+        if (beta == 0.0) {
+          conv = true;
+          dmax = 0.0;
+          break;
+        }
+        // ---- smoother weights: once per sample, from the first slab operator ----
+        if (!weights_ready) {
+          for (int l = 0; l < L->nmg; ++l) {
+            TI* x0 = (l == 0) ? tm.V + vs : tm.mgX(l);
+            TI* x1 = (l == 0) ? tm.V + 2 * vs : tm.mgT(l);
+            const double lmax = 1.05 * tm.power_lmax(l, x0, x1, red);
+            const int K = (l == L->nmg - 1) ? prm.coarse_sweeps : prm.smooth_steps;
+            if (tid == 0) chebyshev_weights(lmax / prm.cheb_ratio, lmax, K, omega_tab + l * kMaxSweeps);
+          }
+          __syncthreads();
+          weights_ready = true;
+        }
+
+        // ---- GMRES(restart), right-preconditioned by the V-cycle ----
+        if (tid == 0) {
+          sc[0] = 1.0 / beta;
+          gv[0] = beta;
+        }
+        __syncthreads();
+        const double tol_abs = eta * beta;
+        int jdim = 0;
+        for (int j = 0; j < restart; ++j) {
+          TI* Vj = tm.V + j * vs;
+          TI* Zj = tm.Z + j * vs;
+          TI* Vn = tm.V + (j + 1) * vs;
+          tm.vcycle(Vj, Zj);
+          // pass A: ws = A Z_j (into V_{j+1}), dots with V_0..V_min(j,7)
+          double d[9];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) d[q] = 0.0;
+          const int nk0 = min(j + 1, 8);
+          tm.bytes += (3.0 + nk0) * sizeof(TI) * n0 + tm.dbytes(0);
+          {
+            const TI* __restrict__ Vb = tm.V;
+            tm.template staged<TI>(Zj, tm.mgW(0), [&](int i, int jj, int kk, int idx, auto& A, auto& B, auto& S) {
+              const TI w = apply_at<TI, DIM>(g0, i, jj, kk, [&](int a, int b, int c) { return B(a, b, c) * A(a, b, c); },
+                                             A, S, TI(0), (TI*)nullptr);
+              Vn[idx] = w;
+              const double wd = double(w);
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (q < nk0) d[q] += double(Vb[q * vs + idx]) * wd;
+            });
+          }
+          block_sum<BLOCK, 9>(d, red);
+          if (tid == 0)
+            for (int q = 0; q < nk0; ++q) H[q * kMaxRestart + j] = sc[q] * sc[j] * d[q];
+          for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
+            const int nk = min(j + 1 - k0, 8);
+            tm.bytes += (1.0 + nk) * sizeof(TI) * n0;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) d[q] = 0.0;
+            for (int idx = tid; idx < n0; idx += BLOCK) {
+              const double wd = double(Vn[idx]);
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (q < nk) d[q] += double(tm.V[(k0 + q) * vs + idx]) * wd;
+            }
+            block_sum<BLOCK, 9>(d, red);
+            if (tid == 0)
+              for (int q = 0; q < nk; ++q) H[(k0 + q) * kMaxRestart + j] = sc[k0 + q] * sc[j] * d[q];
+          }
+          if (tid == 0)
+            for (int q = 0; q <= j; ++q) coef[q] = H[q * kMaxRestart + j] * sc[q] / sc[j];
+          __syncthreads();
+          // pass B: V_{j+1} -= sum_q coef_q V_q ; norm
+          double nn[1] = {0.0};
+          tm.bytes += (j + 3.0) * sizeof(TI) * n0;
+          for (int idx = tid; idx < n0; idx += BLOCK) {
+            double w = double(Vn[idx]);
+            for (int q = 0; q <= j; ++q) w -= coef[q] * double(tm.V[q * vs + idx]);
+            const TI wt = TI(w);
+            Vn[idx] = wt;
+            nn[0] += double(wt) * double(wt);
+          }
+          block_sum<BLOCK, 1>(nn, red);
+          const double hn = sqrt(nn[0]);
+          if (tid == 0) {
+            const double hj1 = sc[j] * hn;
+            sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+            for (int q = 0; q < j; ++q) {  // previous rotations on column j
+              const double a = H[q * kMaxRestart + j], b = H[(q + 1) * kMaxRestart + j];
+              H[q * kMaxRestart + j] = cs_[q] * a + sn_[q] * b;
+              H[(q + 1) * kMaxRestart + j] = -sn_[q] * a + cs_[q] * b;
+            }
+            const double a = H[j * kMaxRestart + j];
+            const double r = sqrt(a * a + hj1 * hj1);
+            const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? hj1 / r : 0.0;
+            cs_[j] = c;
+            sn_[j] = sn;
+            H[j * kMaxRestart + j] = r;
+            H[(j + 1) * kMaxRestart + j] = 0.0;
+            gv[j + 1] = -sn * gv[j];
+            gv[j] = c * gv[j];
+            sh_resid = fabs(gv[j + 1]);
+          }
+          __syncthreads();
+          jdim = j + 1;
+          const double resid = sh_resid;
+          if (!(resid > tol_abs) || !(hn > 0.0)) break;
+        }
+        krylov_total += jdim;
+        if (tid == 0) {
+          for (int q = jdim - 1; q >= 0; --q) {
+            double acc = gv[q];
+            for (int p = q + 1; p < jdim; ++p) acc -= H[q * kMaxRestart + p] * yv[p];
+            yv[q] = acc / H[q * kMaxRestart + q];
+          }
+          for (int q = 0; q < jdim; ++q) coef[q] = yv[q] * sc[q];
+        }
+        __syncthreads();
+        // ---- u += sum_q y_q z_q (float64), max-norm of the step ----
+        double dm = 0.0;
+        tm.bytes += double(jdim) * sizeof(TI) * n0 + 16.0 * n0;
+        for (int idx = tid; idx < n0; idx += BLOCK) {
+          double dlt = 0.0;
+          for (int q = 0; q < jdim; ++q) dlt += coef[q] * double(tm.Z[q * vs + idx]);
+          u[idx] += dlt;
+          dm = fmax(dm, fabs(dlt));
+        }
+        dmax = block_max<BLOCK>(dm, red);
+        const double ach = sh_resid / beta;
+        if (!isfinite(dmax)) {
+          status = -5;
+          break;
+        }
+        if (dmax <= prm.newton_tol) {
+          conv = true;
+          ++it;
+          break;
+        }
+        if (it >= 1) {
+          const double ratio = dmax / dprev;
+          const double pred = dmax * fmax(ratio * ratio, 10.0 * ach);
+          if (ratio < 0.5 && pred <= 0.1 * prm.newton_tol) {
+            conv = true;
+            ++it;
+            break;
+          }
+        }
+        dprev = dmax;
+        eta = fmax(prm.gmres_rtol, fmin(1e-4, 0.01 * dmax));
+      }
+      if (status == -5) break;
+      if (!conv && status == 0) status = -4;
+      newton_total += it;
+      newton_max_slab = max(newton_max_slab, it);
+      worst_final = fmax(worst_final, dmax);
+
+      // ---- accept slab k: store, activation crossing, shift history ----
+      double* Uk = Uout + (int64_t)k * n0;
+      const double tk = k * dt;
+      tm.bytes += 40.0 * n0;
+      for (int idx = tid; idx < n0; idx += BLOCK) {
+        const double un = u[idx], up = uprev[idx];
+        Uk[idx] = un;
+        if (tact[idx] < 0.0 && un >= thr) tact[idx] = tk + dt * (thr - up) / (un - up);
+        uprev[idx] = un;
+      }
+      __syncthreads();
+    }
+
+    // ---- finalize the sample ----
+    double cen[1] = {0.0};
+    for (int idx = tid; idx < n0; idx += BLOCK) {
+      double t = tact[idx];
+      if (t < 0.0) {
+        t = L->T;
+        cen[0] += 1.0;
+      }
+      if (task.t_act) task.t_act[(int64_t)s * n0 + idx] = t;
+    }
+    block_sum<BLOCK, 1>(cen, red);
+    if (tid == 0 && task.stats) {
+      SampleStatsDev st;
+      st.status = status;
+      st.newton_max_per_slab = newton_max_slab;
+      st.newton_iters = newton_total;
+      st.krylov_iters = krylov_total;
+      st.final_step = worst_final;
+      st.ticks = wall_clock64() - t_start;
+      st.censored = (int)cen[0];
+      st.pad = 0;
+      st.alg_bytes = tm.bytes;
+      task.stats[s] = st;
+    }
+    prevU = Uout;
+    have_prev = (status == 0);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launcher
+// ---------------------------------------------------------------------------
+template <typename TI, int DIM, int BLOCK>
+static hipError_t launch_one(const LevelDev* levels, const TeamTask* tasks, int n_tasks, SolverParams prm,
+                             size_t lds, hipStream_t st) {
+  auto kern = st_team_kernel<TI, DIM, BLOCK>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(n_tasks), dim3(BLOCK), lds, st, levels, tasks, prm);
+  return hipGetLastError();
+}
+
+template <typename TI, int DIM>
+static hipError_t launch_dim(const LevelDev* levels, const TeamTask* tasks, int n_tasks, SolverParams prm, int block,
+                             size_t lds, hipStream_t st) {
+  switch (block) {
+    case 256: return launch_one<TI, DIM, 256>(levels, tasks, n_tasks, prm, lds, st);
+    case 512: return launch_one<TI, DIM, 512>(levels, tasks, n_tasks, prm, lds, st);
+    case 1024: return launch_one<TI, DIM, 1024>(levels, tasks, n_tasks, prm, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_tasks,
+                              SolverParams prm, int block, size_t lds_bytes, hipStream_t st) {
+  if (n_tasks <= 0) return hipSuccess;
+  if (dim == 2)
+    return inner_fp32 ? launch_dim<float, 2>(levels, tasks, n_tasks, prm, block, lds_bytes, st)
+                      : launch_dim<double, 2>(levels, tasks, n_tasks, prm, block, lds_bytes, st);
+  return inner_fp32 ? launch_dim<float, 3>(levels, tasks, n_tasks, prm, block, lds_bytes, st)
+                    : launch_dim<double, 3>(levels, tasks, n_tasks, prm, block, lds_bytes, st);
+}
+
+}  // namespace stm

@@ -1,0 +1,812 @@
+// C interface of the library (include/stmlmc.h): validation, level setup,
+// workspace management, schedules and the MLMC driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stmlmc.h"
+#include "stm_launch.h"
+
+using namespace stm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct LevelHost {
+  LevelDev dev;          // host copy (device pointers inside)
+  int64_t team_bytes;    // workspace per team without the space-time buffer
+  int64_t u_bytes;       // space-time buffer m * n0 float64
+  double* fib = nullptr; // device fibre table
+};
+
+}  // namespace
+
+struct stm_ctx {
+  stm_problem p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 256;
+  std::string err;
+  std::vector<LevelHost> levels;
+  LevelDev* d_levels = nullptr;  // device copy of all LevelDev
+  SolverParams prm{};
+  bool inner_fp32 = false;
+  // growable device buffers
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  TeamTask* d_tasks = nullptr;
+  size_t tasks_cap = 0;
+  SampleStatsDev* d_stats = nullptr;
+  size_t stats_cap = 0;
+  int* d_int = nullptr;
+  size_t int_cap = 0;
+  double* d_scratch = nullptr;
+  size_t scratch_cap = 0;
+  // phase timing
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  stm_timings tm{};
+  // measured mean device seconds per sample of each level (0 = not measured yet)
+  double measured_cost[STM_MAX_LEVELS] = {0};
+  int stage_bytes = 48 * 1024;   // dynamic LDS per solver workgroup
+};
+
+namespace {
+
+stm_status fail(stm_ctx* c, stm_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+stm_status hip_fail(stm_ctx* c, hipError_t e, const char* where) {
+  return fail(c, STM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define STM_HIP(ctx, call)                                       \
+  do {                                                           \
+    hipError_t _e = (call);                                      \
+    if (_e != hipSuccess) return hip_fail((ctx), _e, #call);     \
+  } while (0)
+
+template <typename T>
+stm_status grow(stm_ctx* c, T** ptr, size_t* cap, size_t need_bytes) {
+  if (need_bytes <= *cap) return STM_OK;
+  if (*ptr) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, need_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, STM_E_NOMEM, "hipMalloc of " + std::to_string(need_bytes) + " bytes failed");
+  }
+  *ptr = static_cast<T*>(p);
+  *cap = need_bytes;
+  return STM_OK;
+}
+
+GridDev make_grid(int dim, int nx, int ny, int nz, double lx, double ly, double lz) {
+  GridDev g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = dim == 3 ? nz : 1;
+  g.n = g.nx * g.ny * g.nz;
+  g.ex = nx - 1;
+  g.ey = ny - 1;
+  g.ez = dim == 3 ? nz - 1 : 1;
+  g.ne = g.ex * g.ey * g.ez;
+  g.hx = lx / (nx - 1);
+  g.hy = ly / (ny - 1);
+  g.hz = dim == 3 ? lz / (nz - 1) : 1.0;
+  return g;
+}
+
+double fiber_angle(const stm_problem& p, double y, double z) {
+  switch (p.fiber_law) {
+    case STM_FIBER_DIAG2D: return M_PI / 4 + 0.5 * y;
+    case STM_FIBER_ROT3D: return -M_PI / 3 + (2 * M_PI / 3) * z / p.lz;
+    case STM_FIBER_X: return 0.0;
+    default: return M_PI / 4;
+  }
+}
+
+stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
+  if (p.dim != 2 && p.dim != 3) return fail(c, STM_E_INVALID, "dim must be 2 or 3");
+  if (!(p.lx > 0 && p.ly > 0 && (p.dim == 2 || p.lz > 0) && p.T > 0))
+    return fail(c, STM_E_INVALID, "box lengths and T must be positive");
+  if (!(p.sigma_f0 > 0) || !(p.transverse_ratio >= 0) || !std::isfinite(p.k_react) || !std::isfinite(p.a_react))
+    return fail(c, STM_E_INVALID, "invalid physical parameters");
+  if (p.n_levels < 1 || p.n_levels > STM_MAX_LEVELS) return fail(c, STM_E_INVALID, "n_levels out of range");
+  if (p.n_modes < 1 || p.n_modes > 256) return fail(c, STM_E_INVALID, "n_modes must be in 1..256");
+  if (p.precision != STM_PREC_FP64 && p.precision != STM_PREC_MIXED) return fail(c, STM_E_INVALID, "bad precision");
+  if (p.fiber_law < 0 || p.fiber_law > 3) return fail(c, STM_E_INVALID, "bad fiber_law");
+  if (p.gmres_restart < 0 || p.gmres_restart > kMaxRestart) return fail(c, STM_E_INVALID, "gmres_restart > 30");
+  if (p.coarse_sweeps < 0 || p.coarse_sweeps > kMaxSweeps || p.smooth_steps < 0 || p.smooth_steps > kMaxSweeps)
+    return fail(c, STM_E_INVALID, "sweep counts must be in 0..32");
+  if (p.smoother < 0 || p.smoother > 1) return fail(c, STM_E_INVALID, "smoother must be 0 or 1");
+  if (p.lds_kb < 0 || p.lds_kb > 160) return fail(c, STM_E_INVALID, "lds_kb must be in 0..160");
+  if (p.block_threads != 0 && p.block_threads != 256 && p.block_threads != 512 && p.block_threads != 1024)
+    return fail(c, STM_E_INVALID, "block_threads must be 0, 256, 512 or 1024");
+  for (int l = 0; l < p.n_levels; ++l) {
+    const stm_level& L = p.levels[l];
+    const int nz = p.dim == 3 ? L.nz : 1;
+    if (L.nx < 3 || L.ny < 3 || (p.dim == 3 && L.nz < 2) || L.m < 1)
+      return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
+    if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
+      return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
+    if (l > 0) {
+      const stm_level& P = p.levels[l - 1];
+      if (L.nx != 2 * P.nx - 1 || L.ny != 2 * P.ny - 1 || (p.dim == 3 && L.nz != 2 * P.nz - 1))
+        return fail(c, STM_E_INVALID, "levels must be nested 2:1 refinements");
+    }
+  }
+  return STM_OK;
+}
+
+void fill_defaults(stm_problem& p) {
+  const bool mixed = p.precision == STM_PREC_MIXED;
+  if (p.newton_tol <= 0) p.newton_tol = mixed ? 1e-10 : 1e-12;
+  if (p.newton_max <= 0) p.newton_max = 30;
+  if (p.gmres_rtol <= 0) p.gmres_rtol = mixed ? 1e-5 : 1e-10;
+  if (p.gmres_restart <= 0) p.gmres_restart = 16;
+  if (p.smooth_steps <= 0) p.smooth_steps = 2;
+  if (p.smooth_omega <= 0) p.smooth_omega = 0.7;
+  if (p.coarse_sweeps <= 0) p.coarse_sweeps = 8;
+  if (p.cheb_ratio <= 1) p.cheb_ratio = p.dim == 2 ? 10.0 : 30.0;
+  if (p.lds_kb <= 0) p.lds_kb = 64;
+  if (p.mg_levels == 0) p.mg_levels = 1;
+  if (p.max_lanes <= 0) p.max_lanes = 1024;
+}
+
+int auto_block(const stm_problem& p, int n0) {
+  if (p.block_threads) return p.block_threads;
+  if (n0 <= 2500) return 256;
+  return 512;
+}
+
+stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
+  const stm_problem& p = c->p;
+  const stm_level& lv = p.levels[l];
+  LevelDev& d = out.dev;
+  std::memset(&d, 0, sizeof(d));
+  d.dim = p.dim;
+  d.m = lv.m;
+  d.T = p.T;
+  d.dt = p.T / lv.m;
+  // multigrid hierarchy: halve while every axis stays odd and >= 3 nodes
+  int nx = lv.nx, ny = lv.ny, nz = p.dim == 3 ? lv.nz : 1;
+  int nmg = 0;
+  const int max_mg = p.mg_levels > 0 ? std::min(p.mg_levels, kMaxMG) : kMaxMG;  // -1: deepest
+  while (true) {
+    d.g[nmg++] = make_grid(p.dim, nx, ny, nz, p.lx, p.ly, p.lz);
+    if (nmg >= max_mg) break;
+    const bool odd = (nx % 2 == 1) && (ny % 2 == 1) && (p.dim == 2 || nz % 2 == 1);
+    const int cx = (nx + 1) / 2, cy = (ny + 1) / 2, cz = (nz + 1) / 2;
+    if (!odd || cx < 5 || cy < 5 || (p.dim == 3 && cz < 3)) break;
+    nx = cx;
+    ny = cy;
+    nz = cz;
+  }
+  d.nmg = nmg;
+  d.ic_cx = p.ic_center[0];
+  d.ic_cy = p.ic_center[1];
+  d.ic_cz = p.dim == 3 ? p.ic_center[2] : 0.0;
+  d.ic_r2 = p.ic_radius * p.ic_radius;
+  // fibre table per element row (2D) / layer (3D)
+  const GridDev& g0 = d.g[0];
+  const int rows = p.dim == 2 ? g0.ey : g0.ez;
+  std::vector<double> fib(3 * rows);
+  for (int r = 0; r < rows; ++r) {
+    const double yc = (r + 0.5) * g0.hy, zc = (r + 0.5) * g0.hz;
+    const double th = p.dim == 2 ? fiber_angle(p, yc, 0.0) : fiber_angle(p, 0.0, zc);
+    const double cth = std::cos(th), sth = std::sin(th);
+    fib[3 * r] = cth * cth;
+    fib[3 * r + 1] = sth * sth;
+    fib[3 * r + 2] = cth * sth;
+  }
+  STM_HIP(c, hipMalloc(&out.fib, fib.size() * sizeof(double)));
+  STM_HIP(c, hipMemcpy(out.fib, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice));
+  d.fib = out.fib;
+  // team workspace layout
+  const size_t ti = c->inner_fp32 ? 4 : 8;
+  const int n0 = g0.n;
+  const size_t vs = (size_t)((n0 + 63) & ~63);
+  const int R = p.gmres_restart;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return (int64_t)o; };
+  d.off_u = take(8 * (size_t)n0);
+  d.off_uprev = take(8 * (size_t)n0);
+  d.off_wk1 = take(8 * (size_t)n0);
+  d.off_tact = take(8 * (size_t)n0);
+  d.off_V = take(ti * vs * (R + 1));
+  d.off_Z = take(ti * vs * R);
+  d.off_rhs = 0;
+  for (int k = 0; k < nmg; ++k) {
+    const GridDev& g = d.g[k];
+    d.off_mgT[k] = take(ti * g.n);
+    d.off_mgW[k] = take(ti * g.n);
+    if (k > 0) {
+      d.off_mgX[k] = take(ti * g.n);
+      d.off_mgB[k] = take(ti * g.n);
+      d.off_mgD[k] = take(ti * 4 * (size_t)g.ne);
+    }
+  }
+  out.team_bytes = (int64_t)off;
+  d.off_U = off;
+  // LDS tiles: maximise interior / staged nodes within the staging budget
+  const size_t budget = (size_t)c->stage_bytes;
+  for (int es = 0; es < 2; ++es) {
+    const size_t fb = es == 0 ? 8 : 4;
+    int by = 1, bz = 1;
+    double best = -1.0;
+    const int zmax = p.dim == 3 ? g0.nz : 1;
+    for (int rz = 1; rz <= zmax; ++rz) {
+      for (int ry = 1; ry <= g0.ny; ++ry) {
+        const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
+        const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
+        const size_t bytes = 2 * fb * (size_t)sy * sz * g0.nx + 16 + 8 * (size_t)ey * ez * g0.ex;
+        if (bytes > budget) break;
+        const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
+        if (eff > best) {
+          best = eff;
+          by = ry;
+          bz = rz;
+        }
+      }
+    }
+    if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
+    if (es == 0) { d.tile_y8 = by; d.tile_z8 = bz; } else { d.tile_y4 = by; d.tile_z4 = bz; }
+  }
+  out.u_bytes = (int64_t)align_up(8 * (size_t)n0 * lv.m);
+  d.team_bytes = out.team_bytes;
+  return STM_OK;
+}
+
+stm_status check_ptr(stm_ctx* c, const void* ptr, const char* name) {
+  if (!ptr) return fail(c, STM_E_INVALID, std::string(name) + " is NULL");
+  return STM_OK;
+}
+
+// Elapsed device time between two events recorded on the context stream.
+stm_status timed_begin(stm_ctx* c) {
+  STM_HIP(c, hipEventRecord(c->ev[0], c->stream));
+  return STM_OK;
+}
+stm_status timed_end(stm_ctx* c, double* acc_ms) {
+  STM_HIP(c, hipEventRecord(c->ev[1], c->stream));
+  STM_HIP(c, hipEventSynchronize(c->ev[1]));
+  float ms = 0.f;
+  STM_HIP(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+  *acc_ms += ms;
+  return STM_OK;
+}
+
+// Launch the team solver over a list of tasks (synchronous).
+stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& tasks, int block) {
+  if (tasks.empty()) return STM_OK;
+  stm_status st = grow(c, &c->d_tasks, &c->tasks_cap, tasks.size() * sizeof(TeamTask));
+  if (st != STM_OK) return st;
+  STM_HIP(c, hipMemcpyAsync(c->d_tasks, tasks.data(), tasks.size() * sizeof(TeamTask), hipMemcpyHostToDevice,
+                            c->stream));
+  if ((st = timed_begin(c))) return st;
+  hipError_t e = launch_team_solver(c->p.dim, c->inner_fp32, c->d_levels, c->d_tasks, (int)tasks.size(), c->prm,
+                                    block, (size_t)c->stage_bytes, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "team solver launch");
+  // the task table stays alive until the kernel has finished
+  if ((st = timed_end(c, &c->tm.solve_ms))) return st;
+  c->tm.solve_launches += 1;
+  c->tm.solve_teams = (int)tasks.size();
+  c->tm.solve_block = block;
+  return STM_OK;
+}
+
+void reset_timings(stm_ctx* c) { c->tm = stm_timings{}; }
+
+}  // namespace
+
+extern "C" {
+
+stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
+  if (!out) return STM_E_INVALID;
+  *out = nullptr;
+  if (!p) return STM_E_INVALID;
+  stm_ctx* c = new stm_ctx();
+  c->p = *p;
+  stm_status st = validate_problem(c, c->p);
+  if (st != STM_OK) {
+    std::fprintf(stderr, "stm_create: %s\n", c->err.c_str());
+    delete c;
+    return st;
+  }
+  fill_defaults(c->p);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->inner_fp32 = c->p.precision == STM_PREC_MIXED;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return STM_E_DEVICE;
+  }
+  {
+    // staging budget: requested KiB, within the per-workgroup LDS limit minus static use
+    int max_lds = 65536;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+      max_lds = 65536;
+    const int static_lds = 13 * 1024;
+    c->stage_bytes = std::min(c->p.lds_kb * 1024, max_lds - static_lds);
+  }
+  c->levels.resize(c->p.n_levels);
+  for (int l = 0; l < c->p.n_levels; ++l) {
+    st = build_level(c, l, c->levels[l]);
+    if (st != STM_OK) {
+      std::fprintf(stderr, "stm_create: %s\n", c->err.c_str());
+      stm_destroy(c);
+      return st;
+    }
+  }
+  if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    stm_destroy(c);
+    return STM_E_DEVICE;
+  }
+  std::vector<LevelDev> lv(c->p.n_levels);
+  for (int l = 0; l < c->p.n_levels; ++l) lv[l] = c->levels[l].dev;
+  if (hipMalloc(&c->d_levels, lv.size() * sizeof(LevelDev)) != hipSuccess ||
+      hipMemcpy(c->d_levels, lv.data(), lv.size() * sizeof(LevelDev), hipMemcpyHostToDevice) != hipSuccess) {
+    stm_destroy(c);
+    return STM_E_DEVICE;
+  }
+  SolverParams& s = c->prm;
+  s.k_react = c->p.k_react;
+  s.a_react = c->p.a_react;
+  s.tau = c->p.transverse_ratio * c->p.sigma_f0;
+  s.threshold = c->p.threshold;
+  s.newton_tol = c->p.newton_tol;
+  s.gmres_rtol = c->p.gmres_rtol;
+  s.smooth_omega = c->p.smooth_omega;
+  s.newton_max = c->p.newton_max;
+  s.restart = c->p.gmres_restart;
+  s.smooth_steps = c->p.smooth_steps;
+  s.coarse_sweeps = c->p.coarse_sweeps;
+  s.smoother = (c->p.smoother == 1) ? 0 : 1;  // kernel: 1 = Chebyshev weights, 0 = fixed
+  s.cheb_ratio = c->p.cheb_ratio;
+  s.power_iters = 10;
+  *out = c;
+  return STM_OK;
+}
+
+void stm_destroy(stm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& l : c->levels)
+    if (l.fib) (void)hipFree(l.fib);
+  if (c->d_levels) (void)hipFree(c->d_levels);
+  if (c->work) (void)hipFree(c->work);
+  if (c->d_tasks) (void)hipFree(c->d_tasks);
+  if (c->d_stats) (void)hipFree(c->d_stats);
+  if (c->d_int) (void)hipFree(c->d_int);
+  if (c->d_scratch) (void)hipFree(c->d_scratch);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* stm_last_error(const stm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+stm_status stm_get_timings(const stm_ctx* c, stm_timings* out) {
+  if (!c || !out) return STM_E_INVALID;
+  *out = c->tm;
+  return STM_OK;
+}
+
+stm_status stm_level_size(const stm_ctx* c, int level, int* n_nodes, int* n_elements, int* m) {
+  if (!c || level < 0 || level >= c->p.n_levels) return STM_E_INVALID;
+  const LevelDev& d = c->levels[level].dev;
+  if (n_nodes) *n_nodes = d.g[0].n;
+  if (n_elements) *n_elements = d.g[0].ne;
+  if (m) *m = d.m;
+  return STM_OK;
+}
+
+stm_status stm_kl_synthesize(stm_ctx* c, int level, const double* modes, const double* xi, int S, double* sigma) {
+  if (!c) return STM_E_INVALID;
+  c->err.clear();
+  if (level < 0 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level out of range");
+  if (S < 0) return fail(c, STM_E_INVALID, "S < 0");
+  if (S == 0) return STM_OK;
+  stm_status st;
+  if ((st = check_ptr(c, modes, "modes")) || (st = check_ptr(c, xi, "xi")) || (st = check_ptr(c, sigma, "sigma")))
+    return st;
+  const int E = c->levels[level].dev.g[0].ne;
+  reset_timings(c);
+  if ((st = timed_begin(c))) return st;
+  hipError_t e = launch_kl_synthesize(modes, xi, sigma, S, E, c->p.n_modes, c->p.sigma_f0,
+                                      c->p.precision == STM_PREC_MIXED, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kl launch");
+  return timed_end(c, &c->tm.kl_ms);
+}
+
+stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
+                        stm_solve_stats* stats_host) {
+  if (!c) return STM_E_INVALID;
+  c->err.clear();
+  if (level < 0 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level out of range");
+  if (S < 0) return fail(c, STM_E_INVALID, "S < 0");
+  if (S == 0) return STM_OK;
+  stm_status st;
+  if ((st = check_ptr(c, sigma, "sigma")) || (st = check_ptr(c, u, "u"))) return st;
+  LevelHost& L = c->levels[level];
+  const int lanes = std::min(S, c->p.max_lanes);
+  if ((st = grow(c, &c->work, &c->work_bytes, (size_t)lanes * L.team_bytes))) return st;
+  if ((st = grow(c, &c->d_stats, &c->stats_cap, (size_t)S * sizeof(SampleStatsDev)))) return st;
+  std::vector<TeamTask> tasks(lanes);
+  for (int i = 0; i < lanes; ++i) {
+    TeamTask& t = tasks[i];
+    t.level = level;
+    t.first = i;
+    t.stride = lanes;
+    t.count = (S - i + lanes - 1) / lanes;
+    t.sigma = sigma;
+    t.u_out = u;
+    t.u_guess = u0_guess;
+    t.t_act = nullptr;
+    t.work = static_cast<unsigned char*>(c->work) + (size_t)i * L.team_bytes;
+    t.stats = c->d_stats;
+  }
+  reset_timings(c);
+  if ((st = run_tasks(c, tasks, auto_block(c->p, L.dev.g[0].n)))) return st;
+  std::vector<SampleStatsDev> sd(S);
+  STM_HIP(c, hipMemcpy(sd.data(), c->d_stats, S * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
+  int worst = 0;
+  for (int s = 0; s < S; ++s) {
+    if (sd[s].status < worst) worst = sd[s].status;
+    c->tm.solve_bytes += sd[s].alg_bytes;
+    if (stats_host) {
+      stm_solve_stats& o = stats_host[s];
+      o.status = sd[s].status;
+      o.newton_max_per_slab = sd[s].newton_max_per_slab;
+      o.newton_iters = sd[s].newton_iters;
+      o.krylov_iters = sd[s].krylov_iters;
+      o.final_step = sd[s].final_step;
+      o.device_seconds = sd[s].ticks * 1e-8;
+      o.algorithmic_bytes = sd[s].alg_bytes;
+    }
+  }
+  if (worst == STM_E_NONFINITE) return fail(c, STM_E_NONFINITE, "non-finite residual in a sample");
+  if (worst == STM_E_NOT_CONVERGED) return fail(c, STM_E_NOT_CONVERGED, "Newton iteration limit reached in a sample");
+  return STM_OK;
+}
+
+stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, double* t_act, int* n_censored_host) {
+  if (!c) return STM_E_INVALID;
+  c->err.clear();
+  if (level < 0 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level out of range");
+  if (S < 0) return fail(c, STM_E_INVALID, "S < 0");
+  if (S == 0) return STM_OK;
+  stm_status st;
+  if ((st = check_ptr(c, u, "u")) || (st = check_ptr(c, t_act, "t_act"))) return st;
+  const LevelDev& d = c->levels[level].dev;
+  int* cen = nullptr;
+  if (n_censored_host) {
+    if ((st = grow(c, &c->d_int, &c->int_cap, (size_t)S * sizeof(int)))) return st;
+    STM_HIP(c, hipMemsetAsync(c->d_int, 0, S * sizeof(int), c->stream));
+    cen = c->d_int;
+  }
+  reset_timings(c);
+  if ((st = timed_begin(c))) return st;
+  hipError_t e = launch_activation_map(d.g[0], d.dim, d.m, d.dt, d.T, c->p.threshold, d.ic_cx, d.ic_cy, d.ic_cz,
+                                       d.ic_r2, u, S, t_act, cen, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "activation launch");
+  if ((st = timed_end(c, &c->tm.stats_ms))) return st;
+  if (n_censored_host) {
+    STM_HIP(c, hipMemcpyAsync(n_censored_host, c->d_int, S * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    STM_HIP(c, hipStreamSynchronize(c->stream));
+  }
+  return STM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// MLMC driver
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Group {          // all fine or all coarse members of one MLMC level
+  int grid;             // level index of the grid solved
+  int mlmc_level;
+  bool coarse;
+  int n0, n1;           // samples [n0, n1) solved in this round
+  double cost;          // estimated cost per sample (nodes x steps)
+  int lanes;
+};
+
+// Lane allocation for one persistent launch: pick the smallest makespan
+// target T such that giving each group ceil(N_g / floor(T / c_g)) lanes fits
+// the lane budget (every lane of a group then solves at most floor(T / c_g)
+// samples in sequence, each warm-started from the previous one).
+void allocate_lanes(std::vector<Group>& gs, int budget) {
+  double total = 0.0, biggest = 0.0;
+  for (auto& g : gs) {
+    total += (g.n1 - g.n0) * g.cost;
+    biggest = std::max(biggest, g.cost);
+  }
+  double T = std::max(biggest, total / std::max(budget, 1));
+  for (int iter = 0; iter < 200; ++iter) {
+    int used = 0;
+    for (auto& g : gs) {
+      const int N = g.n1 - g.n0;
+      const int per = std::max(1, (int)std::floor(T / g.cost + 1e-9));
+      g.lanes = N > 0 ? (N + per - 1) / per : 0;
+      used += g.lanes;
+    }
+    if (used <= budget) return;
+    T *= 1.05;
+  }
+}
+
+}  // namespace
+
+extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const double* const* modes_host,
+                                        const double* const* xi_host, const int* capacity_host, double target_rmse,
+                                        int pilot, stm_mlmc_result* out) {
+  if (!c) return STM_E_INVALID;
+  c->err.clear();
+  stm_status st;
+  if (!modes_host || !xi_host || !out) return fail(c, STM_E_INVALID, "modes, xi and out are required");
+  if (!out->mean || !out->var) return fail(c, STM_E_INVALID, "out->mean and out->var are required");
+  const int L1 = c->p.n_levels;
+  const int M = c->p.n_modes;
+  std::vector<int> cap(L1), N(L1, 0);
+  for (int l = 0; l < L1; ++l) {
+    if (!modes_host[l] || !xi_host[l]) return fail(c, STM_E_INVALID, "modes/xi pointer of a level is NULL");
+    cap[l] = capacity_host ? capacity_host[l] : (N_host ? N_host[l] : 0);
+    if (N_host) {
+      if (N_host[l] < 2) return fail(c, STM_E_INVALID, "each level needs at least 2 samples");
+      if (N_host[l] > cap[l]) return fail(c, STM_E_INVALID, "N exceeds capacity");
+    }
+  }
+  const bool adaptive = (N_host == nullptr);
+  if (adaptive) {
+    if (!(target_rmse > 0) || pilot < 2) return fail(c, STM_E_INVALID, "adaptive mode needs target_rmse > 0, pilot >= 2");
+    for (int l = 0; l < L1; ++l)
+      if (cap[l] < pilot) return fail(c, STM_E_INVALID, "capacity below pilot");
+  }
+  const LevelDev& dL = c->levels[L1 - 1].dev;
+  const int nL = dL.g[0].n;
+  // device buffers: sigma and activation maps of every sample (fine and coarse members)
+  std::vector<size_t> off_sf(L1), off_sc(L1), off_tf(L1), off_tc(L1);
+  size_t tot = 0;
+  for (int l = 0; l < L1; ++l) {
+    const int nf = c->levels[l].dev.g[0].n, ef = c->levels[l].dev.g[0].ne;
+    off_sf[l] = tot; tot += (size_t)cap[l] * ef;
+    off_tf[l] = tot; tot += (size_t)cap[l] * nf;
+    if (l > 0) {
+      const int nc = c->levels[l - 1].dev.g[0].n, ec = c->levels[l - 1].dev.g[0].ne;
+      off_sc[l] = tot; tot += (size_t)cap[l] * ec;
+      off_tc[l] = tot; tot += (size_t)cap[l] * nc;
+    }
+  }
+  int max_cap = 0;
+  for (int l = 0; l < L1; ++l) max_cap = std::max(max_cap, cap[l]);
+  const int chunk = 64;
+  const size_t part_sz = (size_t)((max_cap + chunk - 1) / chunk) * 6 * nL;
+  const size_t vpart_sz = (size_t)(nL + 255) / 256;
+  const size_t off_part = tot; tot += part_sz;
+  const size_t off_vpart = tot; tot += vpart_sz;
+  if ((st = grow(c, &c->d_scratch, &c->scratch_cap, tot * sizeof(double)))) return st;
+  double* S0 = c->d_scratch;
+  // per-sample stats for every (level, member, sample)
+  std::vector<size_t> off_stf(L1), off_stc(L1);
+  size_t nst = 0;
+  for (int l = 0; l < L1; ++l) {
+    off_stf[l] = nst; nst += cap[l];
+    off_stc[l] = nst; nst += cap[l];
+  }
+  if ((st = grow(c, &c->d_stats, &c->stats_cap, nst * sizeof(SampleStatsDev)))) return st;
+
+  std::vector<int> Ndone(L1, 0);
+  std::vector<int> Ntarget(L1);
+  for (int l = 0; l < L1; ++l) Ntarget[l] = adaptive ? pilot : N_host[l];
+  std::vector<double> V(L1, 0.0), cost(L1, 0.0);
+  std::vector<double> level_norm(L1, 0.0);
+  std::vector<SampleStatsDev> sh(nst);
+  int rounds = 0;
+  int worst = 0;
+  const bool mixed = c->p.precision == STM_PREC_MIXED;
+  const int lane_budget = c->p.max_lanes;
+
+  reset_timings(c);
+  while (true) {
+    ++rounds;
+    if ((st = timed_begin(c))) return st;
+    // 1) KL synthesis for the new samples of every level (fine and coarse member share xi)
+    for (int l = 0; l < L1; ++l) {
+      const int n0 = Ndone[l], n1 = Ntarget[l];
+      if (n1 <= n0) continue;
+      const int ef = c->levels[l].dev.g[0].ne;
+      hipError_t e = launch_kl_synthesize(modes_host[l], xi_host[l] + (size_t)n0 * M, S0 + off_sf[l] + (size_t)n0 * ef,
+                                          n1 - n0, ef, M, c->p.sigma_f0, mixed, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "kl launch");
+      if (l > 0) {
+        const int ec = c->levels[l - 1].dev.g[0].ne;
+        e = launch_kl_synthesize(modes_host[l - 1], xi_host[l] + (size_t)n0 * M, S0 + off_sc[l] + (size_t)n0 * ec,
+                                 n1 - n0, ec, M, c->p.sigma_f0, mixed, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "kl launch");
+      }
+    }
+    if ((st = timed_end(c, &c->tm.kl_ms))) return st;
+    // 2) one persistent launch over all groups
+    std::vector<Group> gs;
+    for (int l = 0; l < L1; ++l) {
+      if (Ntarget[l] <= Ndone[l]) continue;
+      for (int cm = 0; cm < (l > 0 ? 2 : 1); ++cm) {
+        Group g;
+        g.grid = cm ? l - 1 : l;
+        g.mlmc_level = l;
+        g.coarse = cm == 1;
+        g.n0 = Ndone[l];
+        g.n1 = Ntarget[l];
+        const LevelDev& d = c->levels[g.grid].dev;
+        // model: nodes x steps plus a per-slab overhead (small grids are
+        // dominated by the per-pass synchronisation); measured costs win
+        g.cost = (double)(d.g[0].n + 3000) * d.m;
+        g.lanes = 0;
+        gs.push_back(g);
+      }
+    }
+    bool all_measured = true;
+    for (auto& g : gs) all_measured = all_measured && c->measured_cost[g.grid] > 0;
+    if (all_measured)
+      for (auto& g : gs) g.cost = c->measured_cost[g.grid];
+    allocate_lanes(gs, lane_budget);
+    size_t ws = 0;
+    for (auto& g : gs) ws += (size_t)g.lanes * (c->levels[g.grid].team_bytes + c->levels[g.grid].u_bytes);
+    if ((st = grow(c, &c->work, &c->work_bytes, ws))) return st;
+    std::vector<TeamTask> tasks;
+    size_t woff = 0;
+    int block = 256;
+    for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
+    for (auto& g : gs) {
+      const LevelHost& LH = c->levels[g.grid];
+      const int l = g.mlmc_level;
+      const int N = g.n1 - g.n0;
+      for (int i = 0; i < g.lanes; ++i) {
+        TeamTask t;
+        t.level = g.grid;
+        t.first = g.n0 + i;
+        t.stride = g.lanes;
+        t.count = (N - i + g.lanes - 1) / g.lanes;
+        t.sigma = S0 + (g.coarse ? off_sc[l] : off_sf[l]);
+        t.u_out = nullptr;
+        t.u_guess = nullptr;
+        t.t_act = S0 + (g.coarse ? off_tc[l] : off_tf[l]);
+        t.work = static_cast<unsigned char*>(c->work) + woff;
+        t.stats = c->d_stats + (g.coarse ? off_stc[l] : off_stf[l]);
+        woff += LH.team_bytes + LH.u_bytes;
+        tasks.push_back(t);
+      }
+    }
+    if ((st = run_tasks(c, tasks, block))) return st;
+    for (int l = 0; l < L1; ++l) Ndone[l] = std::max(Ndone[l], Ntarget[l]);
+    // 3) statistics over all samples so far
+    if (out->level_mean == nullptr || out->level_var == nullptr) {
+      // level fields are still needed internally only as scalars
+    }
+    if ((st = timed_begin(c))) return st;
+    hipError_t e = launch_fill(out->mean, 0.0, nL, c->stream);
+    if (e == hipSuccess) e = launch_fill(out->var, 0.0, nL, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fill");
+    std::vector<double> vpart(vpart_sz);
+    double vol = c->p.lx * c->p.ly * (c->p.dim == 3 ? c->p.lz : 1.0);
+    for (int l = 0; l < L1; ++l) {
+      StatsLevelArgs a{};
+      a.gf = c->levels[l].dev.g[0];
+      a.gc = l > 0 ? c->levels[l - 1].dev.g[0] : a.gf;
+      a.gL = dL.g[0];
+      a.dim = c->p.dim;
+      a.tf = S0 + off_tf[l];
+      a.tc = l > 0 ? S0 + off_tc[l] : nullptr;
+      a.N = Ndone[l];
+      a.chunk = chunk;
+      a.part = S0 + off_part;
+      a.mean = out->mean;
+      a.var = out->var;
+      a.level_mean = out->level_mean ? out->level_mean + (size_t)l * nL : nullptr;
+      a.level_var = out->level_var ? out->level_var + (size_t)l * nL : nullptr;
+      a.vpart = S0 + off_vpart;
+      e = launch_level_stats(a, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "stats launch");
+      if (l == L1 - 1) {
+        if ((st = timed_end(c, &c->tm.stats_ms))) return st;
+      }
+      STM_HIP(c, hipMemcpyAsync(vpart.data(), S0 + off_vpart, vpart_sz * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+      STM_HIP(c, hipStreamSynchronize(c->stream));
+      double sum = 0.0;
+      for (double v : vpart) sum += v;
+      V[l] = sum / vol;
+    }
+    // per-level mean norms for the bias estimate
+    if (out->level_mean) {
+      std::vector<double> lm(nL);
+      for (int l = 0; l < L1; ++l) {
+        STM_HIP(c, hipMemcpy(lm.data(), out->level_mean + (size_t)l * nL, nL * sizeof(double), hipMemcpyDeviceToHost));
+        double s2 = 0.0;
+        for (double v : lm) s2 += v * v;
+        level_norm[l] = std::sqrt(s2 / nL);
+      }
+    }
+    STM_HIP(c, hipMemcpy(sh.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
+    for (int l = 0; l < L1; ++l) {
+      double t = 0.0, tf = 0.0;
+      for (int i = 0; i < Ndone[l]; ++i) {
+        tf += sh[off_stf[l] + i].ticks * 1e-8;
+        if (l > 0) t += sh[off_stc[l] + i].ticks * 1e-8;
+      }
+      t += tf;
+      cost[l] = t / std::max(1, Ndone[l]);
+      if (Ndone[l] > 0) c->measured_cost[l] = tf / Ndone[l];
+    }
+    if (!adaptive) break;
+    // 4) Giles allocation: N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k))
+    double ssum = 0.0;
+    for (int l = 0; l < L1; ++l) ssum += std::sqrt(std::max(V[l], 0.0) * cost[l]);
+    bool grow_any = false;
+    for (int l = 0; l < L1; ++l) {
+      const double Vl = std::max(V[l], 0.0);
+      int want = (int)std::ceil(2.0 / (target_rmse * target_rmse) * std::sqrt(Vl / std::max(cost[l], 1e-12)) * ssum);
+      want = std::max(want, Ndone[l]);
+      want = std::min(want, cap[l]);
+      Ntarget[l] = want;
+      if (want > Ndone[l]) grow_any = true;
+    }
+    if (!grow_any || rounds >= 20) break;
+  }
+  // summarise
+  out->rounds = rounds;
+  out->newton_iters = 0;
+  out->krylov_iters = 0;
+  out->censored = 0;
+  out->algorithmic_bytes = 0.0;
+  out->dof_steps = 0;
+  for (int l = 0; l < L1; ++l) {
+    out->N[l] = Ndone[l];
+    out->V[l] = V[l];
+    out->cost[l] = cost[l];
+    for (int cm = 0; cm < (l > 0 ? 2 : 1); ++cm) {
+      const size_t base = cm ? off_stc[l] : off_stf[l];
+      for (int i = 0; i < Ndone[l]; ++i) {
+        const SampleStatsDev& s = sh[base + i];
+        out->newton_iters += s.newton_iters;
+        out->krylov_iters += s.krylov_iters;
+        out->censored += s.censored;
+        out->algorithmic_bytes += s.alg_bytes;
+        worst = std::min(worst, s.status);
+      }
+      const LevelDev& dg = c->levels[cm ? l - 1 : l].dev;
+      out->dof_steps += (int64_t)Ndone[l] * dg.g[0].n * dg.m;
+    }
+  }
+  // bias estimate from the decay of the level corrections
+  out->bias_estimate = 0.0;
+  if (L1 >= 3 && level_norm[L1 - 1] > 0 && level_norm[L1 - 2] > 0) {
+    double alpha = std::log2(level_norm[L1 - 2] / level_norm[L1 - 1]);
+    if (alpha > 0.1) out->bias_estimate = level_norm[L1 - 1] / (std::pow(2.0, alpha) - 1.0);
+  }
+  out->worst_status = worst;
+  c->tm.solve_bytes = out->algorithmic_bytes;
+  if (worst == STM_E_NONFINITE) return fail(c, STM_E_NONFINITE, "non-finite residual in a sample");
+  if (worst == STM_E_NOT_CONVERGED) return fail(c, STM_E_NOT_CONVERGED, "Newton iteration limit reached in a sample");
+  return STM_OK;
+}

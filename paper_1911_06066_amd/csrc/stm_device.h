@@ -1,0 +1,146 @@
+// Device-side data structures and helpers shared by the kernels of the
+// space-time MLMC library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stm {
+
+constexpr int kMaxMG = 8;        // multigrid grids per MLMC level
+constexpr int kMaxRestart = 30;  // Krylov dimension limit
+constexpr int kWave = 64;
+
+// One structured grid: nodes per axis, elements per axis, spacing.
+struct GridDev {
+  int nx, ny, nz;
+  int n;              // nodes
+  int ex, ey, ez;     // elements per axis
+  int ne;             // elements
+  double hx, hy, hz;
+};
+
+// One MLMC level: its grid (index 0) and the coarser grids of its V-cycle.
+// Byte offsets locate every array inside a team workspace.
+struct LevelDev {
+  int dim;
+  int m;
+  double dt, T;
+  int nmg;                      // multigrid grids (>= 1)
+  GridDev g[kMaxMG];
+  const double* fib;            // grid-0 fibre table: per element row (2D) / layer (3D): c^2, s^2, c s
+  double ic_cx, ic_cy, ic_cz, ic_r2;
+  // team workspace layout (bytes from the team base)
+  int64_t off_u, off_uprev, off_wk1, off_tact;          // float64 [n0]
+  int64_t off_V, off_Z;                                 // inner [restart+1][n0], [restart][n0]
+  int64_t off_rhs;                                      // inner [n0] (restart right-hand side)
+  int64_t off_mgX[kMaxMG], off_mgT[kMaxMG], off_mgB[kMaxMG], off_mgW[kMaxMG];  // inner [n_l]
+  int64_t off_mgD[kMaxMG];                              // inner [ne_l][4] element tensors (l >= 1)
+  int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
+  int64_t team_bytes;
+  // LDS tiles of grid-0 stencil passes: node rows (y) and planes (z) per
+  // tile, for 8-byte (index 0) and 4-byte (index 1) staged fields
+  int tile_y8, tile_z8, tile_y4, tile_z4;
+};
+
+// Physics and solver parameters (uniform across a launch).
+struct SolverParams {
+  double k_react, a_react;
+  double tau;           // transverse conductivity
+  double threshold;
+  double newton_tol;
+  double gmres_rtol;
+  double smooth_omega;
+  int newton_max;
+  int restart;
+  int smooth_steps;
+  int coarse_sweeps;
+  int smoother;         // 0: fixed weight omega; 1: Chebyshev-root weights over [lmax/ratio, lmax]
+  double cheb_ratio;
+  int power_iters;      // power iterations estimating lmax(D^-1 A) per sample and grid
+};
+
+constexpr int kMaxSweeps = 32;
+
+// A team (one workgroup) solves `count` samples s = first + i * stride in order.
+struct TeamTask {
+  int level;                 // index into the LevelDev table of the launch
+  int first, stride, count;
+  const double* sigma;       // [*][ne0]
+  double* u_out;             // [*][m][n0] or null (use the team buffer)
+  const double* u_guess;     // [*][m][n0] or null
+  double* t_act;             // [*][n0] or null
+  unsigned char* work;       // team workspace
+  struct SampleStatsDev* stats;  // [*] or null
+};
+
+struct SampleStatsDev {
+  int status;
+  int newton_max_per_slab;
+  long long newton_iters;
+  long long krylov_iters;
+  double final_step;
+  long long ticks;           // wall-clock ticks (100 MHz) spent on the sample
+  int censored;
+  int pad;
+  double alg_bytes;          // bytes the sample's passes must move (per-pass model)
+};
+
+// ---------------------------------------------------------------------------
+// wave64 / block reductions (deterministic: fixed shuffle tree, fixed wave order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Sum NV values over the block; every thread receives the totals.
+// scratch: shared double[NWAVES * NV].  Contains two barriers.
+template <int BLOCK, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[wid * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += scratch[w * NV + i];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+template <int BLOCK>
+__device__ __forceinline__ double block_max(double v, double* scratch) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  v = wave_max(v);
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = scratch[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) s = fmax(s, scratch[w]);
+  __syncthreads();
+  return s;
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return isfinite(x); }
+
+}  // namespace stm

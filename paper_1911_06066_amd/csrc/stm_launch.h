@@ -1,0 +1,45 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "stm_device.h"
+
+namespace stm {
+
+// Fused team solver: one workgroup per task (see st_solver.hip).
+// lds_bytes: dynamic LDS of each workgroup (staging tiles).
+hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_tasks,
+                              SolverParams prm, int block, size_t lds_bytes, hipStream_t st);
+
+// sigma[s][e] = sigma_f0 * exp(sum_k modes[e][k] xi[s][k]) on the matrix cores.
+// split_fp16: operands split into fp16 hi/lo pairs, fp32 accumulation; else float64 MFMA.
+hipError_t launch_kl_synthesize(const double* modes, const double* xi, double* sigma, int S, int E, int M,
+                                double sigma_f0, bool split_fp16, hipStream_t st);
+
+// Activation map of u[S][m][n] with initial state given by the ball (cx, cy, cz, r2) on grid g.
+hipError_t launch_activation_map(const GridDev& g, int dim, int m, double dt, double T, double thr, double cx,
+                                 double cy, double cz, double r2, const double* u, int S, double* t_act,
+                                 int* censored_dev, hipStream_t st);
+
+// MLMC statistics of one level on the finest grid.
+struct StatsLevelArgs {
+  GridDev gf;            // grid of level l
+  GridDev gc;            // grid of level l-1 (unused when tc == null)
+  GridDev gL;            // finest grid
+  int dim;
+  const double* tf;      // [N][gf.n]
+  const double* tc;      // [N][gc.n] or null
+  int N;
+  int chunk;             // samples per Welford chunk
+  double* part;          // [n_chunks][6][gL.n] partial states
+  double* mean;          // [gL.n] accumulated MLMC mean
+  double* var;           // [gL.n] accumulated MLMC variance
+  double* level_mean;    // [gL.n] or null
+  double* level_var;     // [gL.n] or null
+  double* vpart;         // [ceil(gL.n / 256)] partial sums of w_p s^2(Y_l)
+};
+hipError_t launch_level_stats(const StatsLevelArgs& a, hipStream_t st);
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
+
+}  // namespace stm

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C interface vs the CPU oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the grids still span
+several workgroup sweeps, multigrid levels and ragged tails.  Tolerances:
+float64 path 1e-9 relative in u and in the activation map; mixed path
+1e-6 T in activation time and 1e-4 relative in the MLMC variance.
+"""
+
+import numpy as np
+import pytest
+
+import oracle.api as oapi
+from oracle import mlmc as omlmc
+import stinputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _wl(**kw):
+    base = dict(levels=[(17, 17)], steps=[16], n_modes=8, kl_grid=(17, 17), ic_radius=0.25, sigma_f0=4e-3)
+    base.update(kw)
+    return stinputs.workload("small_mc_2d", **base)
+
+
+def _inputs(wl, S, seed_level=0):
+    basis = oapi.kl_basis(wl)
+    modes = [oapi.kl_modes(wl, l, basis) for l in range(len(wl["levels"]))]
+    xi = stinputs.xi(wl["name"], seed_level, S, wl["n_modes"])
+    return modes, xi
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# KL synthesis
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("S,shape,M", [(1, (5, 5), 3), (37, (33, 33), 16), (130, (17, 21), 64), (16, (9, 9), 128)])
+def test_kl_synthesize_fp64(torch_dev, S, shape, M):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[shape], n_modes=M, kl_grid=(13, 13))
+    modes, _ = _inputs(wl, 1)
+    xi = stinputs.normal_field((S, M), seed=S + M)
+    ctx = Context(wl)
+    sig = ctx.kl_synthesize(0, torch.from_numpy(modes[0]).to(dev), torch.from_numpy(xi).to(dev))
+    ref = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    assert _rel(sig.cpu().numpy(), ref) < 1e-14
+
+
+@pytest.mark.parametrize("S,shape,M", [(37, (33, 33), 16), (130, (17, 21), 64), (5, (9, 9), 128)])
+def test_kl_synthesize_split_fp16(torch_dev, S, shape, M):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[shape], n_modes=M, kl_grid=(13, 13))
+    modes, _ = _inputs(wl, 1)
+    xi = stinputs.normal_field((S, M), seed=S + 2 * M)
+    ctx = Context(wl, precision="mixed")
+    sig = ctx.kl_synthesize(0, torch.from_numpy(modes[0]).to(dev), torch.from_numpy(xi).to(dev))
+    ref = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    err = np.abs(np.log(sig.cpu().numpy() / ref)).max()
+    assert err < 1e-6, err
+
+
+# ---------------------------------------------------------------------------
+# space-time solve + activation map, float64
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,m,S", [((17, 17), 16, 3), ((33, 33), 24, 2), ((21, 13), 10, 2), ((5, 5), 4, 1)])
+def test_st_solve_fp64_matches_oracle(torch_dev, shape, m, S):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[shape], steps=[m])
+    modes, xi = _inputs(wl, S)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    U_ref, _ = oapi.st_solve(wl, 0, sig)
+    assert all(s["status"] == 0 for s in stats), stats
+    assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+    t, cen = ctx.activation_map(0, u)
+    t_ref, cen_ref = oapi.activation_map(wl, 0, U_ref)
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+    assert list(cen) == list(cen_ref)
+
+
+def test_st_solve_small_mc_workload_grid(torch_dev):
+    """The 33^2 x 64-step grid of the single-level workload, 2 samples."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("small_mc_2d", kl_grid=(21, 21))
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+    t, cen = ctx.activation_map(0, u)
+    t_ref, cen_ref = oapi.activation_map(wl, 0, U_ref)
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+
+
+def test_warm_start_and_explicit_guess_reach_same_solution(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl()
+    modes, xi = _inputs(wl, 6)
+    sig = torch.from_numpy(oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])).to(dev)
+    a, _ = Context(wl, max_lanes=6).st_solve(0, sig)          # one sample per lane
+    b, sb = Context(wl, max_lanes=2).st_solve(0, sig)         # lanes reuse previous samples
+    c, _ = Context(wl, max_lanes=6).st_solve(0, sig, u0_guess=a.flip(0).contiguous())
+    assert _rel(b.cpu().numpy(), a.cpu().numpy()) < 1e-10
+    assert _rel(c.cpu().numpy(), a.cpu().numpy()) < 1e-10
+
+
+def test_activation_map_kernel_vs_oracle_on_synthetic_series(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[(9, 7)], steps=[12])
+    n, m = 63, 12
+    rng = np.random.default_rng(4)
+    U = np.cumsum(rng.uniform(-0.05, 0.12, (3, m, n)), axis=1)
+    ctx = Context(wl)
+    t, cen = ctx.activation_map(0, torch.from_numpy(U).to(dev))
+    t_ref, cen_ref = oapi.activation_map(wl, 0, U)
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-12
+    assert list(cen) == list(cen_ref)
+
+
+# ---------------------------------------------------------------------------
+# 3D
+# ---------------------------------------------------------------------------
+
+def test_st_solve_3d_fp64_matches_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("slab3d", levels=[(9, 9, 5)], steps=[8], n_modes=8, kl_grid=(9, 9, 3),
+                           precision="fp64", ic_radius=0.3, sigma_f0=4e-3)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    U_ref, _ = oapi.st_solve(wl, 0, sig)
+    assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+    t, cen = ctx.activation_map(0, u)
+    t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+
+
+# ---------------------------------------------------------------------------
+# mixed precision
+# ---------------------------------------------------------------------------
+
+def test_st_solve_mixed_activation_within_tolerance(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[(33, 33)], steps=[32])
+    modes, xi = _inputs(wl, 3)
+    ctx = Context(wl, precision="mixed")
+    sig = ctx.kl_synthesize(0, torch.from_numpy(modes[0]).to(dev), torch.from_numpy(xi).to(dev))
+    u, stats = ctx.st_solve(0, sig)
+    t, cen = ctx.activation_map(0, u)
+    sig_ref = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    U_ref, _ = oapi.st_solve(wl, 0, sig_ref, mode="timestep")
+    t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-6 * wl["T"]
+
+
+# ---------------------------------------------------------------------------
+# MLMC estimator
+# ---------------------------------------------------------------------------
+
+def _mlmc_case(precision):
+    wl = stinputs.workload("mlmc3_2d", levels=[(9, 9), (17, 17), (33, 33)], steps=[8, 16, 32], n_modes=8,
+                           kl_grid=(17, 17), ic_radius=0.25, sigma_f0=4e-3, precision=precision)
+    N = [12, 6, 3]
+    basis = oapi.kl_basis(wl)
+    modes = [oapi.kl_modes(wl, l, basis) for l in range(3)]
+    xi = [stinputs.xi("mlmc3_2d", l, N[l], wl["n_modes"]) for l in range(3)]
+    return wl, N, modes, xi
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mlmc_estimate_matches_oracle(torch_dev, precision):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl, N, modes, xi = _mlmc_case(precision)
+    ctx = Context(wl)
+    out = ctx.mlmc_estimate(N, [torch.from_numpy(m).to(dev) for m in modes],
+                            [torch.from_numpy(x).to(dev) for x in xi])
+    ref = oapi.mlmc_estimate(wl, N, xi, modes, solve_mode="timestep")
+    T = wl["T"]
+    mean = out["mean"].cpu().numpy()
+    var = out["var"].cpu().numpy()
+    if precision == "fp64":
+        assert np.abs(mean - ref["mean"]).max() <= 1e-9 * T
+        assert np.abs(var - ref["var"]).max() <= 1e-9 * max(np.abs(ref["var"]).max(), 1e-12)
+        np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8, atol=1e-15)
+    else:
+        assert np.abs(mean - ref["mean"]).max() <= 1e-6 * T
+        scale = np.linalg.norm(ref["var"])
+        assert np.linalg.norm(var - ref["var"]) <= 1e-4 * scale
+    assert out["N"] == N
+    # level fields
+    lm = out["level_mean"].cpu().numpy()
+    for l in range(3):
+        assert np.abs(lm[l] - ref["level_mean"][l]).max() <= (1e-9 if precision == "fp64" else 1e-6) * T
