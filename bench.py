@@ -164,7 +164,7 @@ def main():
         },
         "detail": {
             "kl_ms": tm["kl_ms"], "solve_ms": tm["solve_ms"], "stats_ms": tm["stats_ms"],
-            "teams": tm["solve_teams"], "block": tm["solve_block"],
+            "teams": tm["solve_teams"], "workgroups": tm["solve_blocks"], "block": tm["solve_block"],
             "newton_iters": out["newton_iters"], "krylov_iters": out["krylov_iters"],
             "algorithmic_bytes": out["algorithmic_bytes"], "censored_nodes": out["censored"],
             "V": out["V"], "cost_s": out["cost"],

@@ -89,7 +89,8 @@ typedef struct {
   int n_modes;                /* KL modes M, 1 .. 256 */
   int precision;              /* stm_precision */
   /* solver controls; 0 selects the default */
-  double newton_tol;          /* max-norm Newton step per slab: 1e-12 (fp64), 1e-10 (mixed) */
+  double newton_tol;          /* max-norm Newton step per slab (u is O(1)): 1e-10; a slab stops when its
+                                 step or the step predicted from the observed contraction is below it */
   int newton_max;             /* Newton iterations per slab: 30 */
   double gmres_rtol;          /* relative Krylov residual: 1e-10 (fp64), 1e-5 (mixed) */
   int gmres_restart;          /* Krylov dimension of one linear solve: 16, at most 30; an unfinished
@@ -104,9 +105,11 @@ typedef struct {
                                  [lmax/cheb_ratio, lmax] of D^-1 A, lmax by power iteration;
                                  1: the fixed weight smooth_omega */
   double cheb_ratio;          /* 10 (2D), 30 (3D) */
-  int lds_kb;                 /* LDS staging budget per workgroup in KiB: 64 */
+  int lds_kb;                 /* LDS staging budget per workgroup in KiB: 144 */
   int block_threads;          /* threads per workgroup: chosen from the grid size */
-  int max_lanes;              /* concurrent samples in flight per call: 1024 */
+  int max_lanes;              /* workgroups per solver launch: 1024 (capped by co-residency) */
+  int team_size;              /* workgroups per sample in stm_st_solve: 0 = chosen from S and the
+                                 device; >1 only with mg_levels = 1 */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */
@@ -119,6 +122,9 @@ typedef struct {
   double device_seconds;      /* wall time of this sample on its workgroup(s) */
   double algorithmic_bytes;   /* bytes the solve's passes must move: each array a pass reads or
                                  writes counted once per pass (cache re-reads not counted) */
+  double phase_seconds[8];    /* per-phase device time (residual, smoothing, Arnoldi stencil, dots,
+                                 orthogonalisation, update, -, -) in libraries built with phase
+                                 timers; zero otherwise */
 } stm_solve_stats;
 
 /* Device time of the last call's phases, measured with HIP events on the context stream. */
@@ -128,7 +134,8 @@ typedef struct {
   double stats_ms;            /* activation / MLMC statistics launches */
   double solve_bytes;         /* algorithmic bytes of the solver launches (sum over samples) */
   int solve_launches;
-  int solve_teams;            /* workgroups of the last solver launch */
+  int solve_teams;            /* teams (samples in flight) of the last solver launch */
+  int solve_blocks;           /* workgroups of the last solver launch */
   int solve_block;            /* threads per workgroup of the last solver launch */
 } stm_timings;
 
@@ -141,7 +148,7 @@ typedef struct {
   /* host-side outputs */
   int N[STM_MAX_LEVELS];      /* samples used per level */
   double V[STM_MAX_LEVELS];   /* |D|^-1 int s^2(Y_l) (lumped quadrature on the finest grid) */
-  double cost[STM_MAX_LEVELS];/* mean device seconds per sample pair of the level */
+  double cost[STM_MAX_LEVELS];/* workgroup-seconds per sample pair of the level (measured) */
   double bias_estimate;       /* |D|^-1/2 || mean(Y_L) ||_2 / (2^alpha - 1), alpha fitted (0 if L < 2) */
   int64_t newton_iters;       /* over all samples */
   int64_t krylov_iters;

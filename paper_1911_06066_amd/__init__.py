@@ -156,7 +156,8 @@ class Context:
             return out, None
         return out, [dict(status=s.status, newton_max_per_slab=s.newton_max_per_slab,
                           newton_iters=s.newton_iters, krylov_iters=s.krylov_iters,
-                          final_step=s.final_step, device_seconds=s.device_seconds)
+                          final_step=s.final_step, device_seconds=s.device_seconds,
+                          algorithmic_bytes=s.algorithmic_bytes, phase_seconds=list(s.phase_seconds))
                      for s in st_arr[:S]]
 
     def activation_map(self, level, u, out=None):

@@ -7,7 +7,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libstmlmc.so")
+LIB_PATH = os.environ.get("STM_LIBRARY", os.path.join(HERE, "libstmlmc.so"))
 
 STM_MAX_LEVELS = 8
 
@@ -50,6 +50,7 @@ class StmProblem(ctypes.Structure):
         ("lds_kb", ctypes.c_int),
         ("block_threads", ctypes.c_int),
         ("max_lanes", ctypes.c_int),
+        ("team_size", ctypes.c_int),
     ]
 
 
@@ -59,6 +60,7 @@ class StmSolveStats(ctypes.Structure):
         ("newton_iters", ctypes.c_int64), ("krylov_iters", ctypes.c_int64),
         ("final_step", ctypes.c_double), ("device_seconds", ctypes.c_double),
         ("algorithmic_bytes", ctypes.c_double),
+        ("phase_seconds", ctypes.c_double * 8),
     ]
 
 
@@ -66,7 +68,7 @@ class StmTimings(ctypes.Structure):
     _fields_ = [
         ("kl_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("stats_ms", ctypes.c_double),
         ("solve_bytes", ctypes.c_double), ("solve_launches", ctypes.c_int),
-        ("solve_teams", ctypes.c_int), ("solve_block", ctypes.c_int),
+        ("solve_teams", ctypes.c_int), ("solve_blocks", ctypes.c_int), ("solve_block", ctypes.c_int),
     ]
 
 

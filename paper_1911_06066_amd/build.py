@@ -28,29 +28,34 @@ def hipcc():
     return path
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src, extra=(), build_dir=BUILD_DIR):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr))
     return obj
 
 
-def build(verbose=False):
-    """Compile every source and link libstmlmc.so (always rebuilds)."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose=False, lib=LIB, defines=(), build_dir=BUILD_DIR):
+    """Compile every source and link the library (always rebuilds).
+
+    defines: extra -D flags, e.g. ("STM_PHASE_TIMERS",) for a phase-timed
+    development build written to another path.
+    """
+    os.makedirs(build_dir, exist_ok=True)
+    extra = ["-D" + d for d in defines]
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, extra, build_dir), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

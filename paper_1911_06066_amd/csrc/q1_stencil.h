@@ -155,3 +155,75 @@ __device__ __forceinline__ T q1_apply_3d(const GridDev& g, int i, int j, int k, 
 }
 
 }  // namespace stm
+
+namespace stm {
+
+// ---------------------------------------------------------------------------
+// Element-centred evaluation: the contributions of one element to its
+// vertices, out[v] = (M_e m + K_e k)_v, with the 1D factors applied axis by
+// axis (sum factorisation).  Vertex v = bx + 2 by (+ 4 bz).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void elem_apply_2d(const T (&k)[4], const T (&m)[4], const Tensor2<T>& D, T cxx, T cyy,
+                                              T cm, T (&out)[4]) {
+  const T dx0 = k[1] - k[0], dx1 = k[3] - k[2];
+  const T dy0 = k[2] - k[0], dy1 = k[3] - k[1];
+  const T p0 = cxx * D.xx * (T(2) * dx0 + dx1), p1 = cxx * D.xx * (T(2) * dx1 + dx0);
+  const T q0 = cyy * D.yy * (T(2) * dy0 + dy1), q1 = cyy * D.yy * (T(2) * dy1 + dy0);
+  const T A = T(0.25) * D.xy * (dy0 + dy1), B = T(0.25) * D.xy * (dx0 + dx1);
+  const T r00 = T(2) * m[0] + m[1], r01 = m[0] + T(2) * m[1];  // row by=0: vx = 0, 1
+  const T r10 = T(2) * m[2] + m[3], r11 = m[2] + T(2) * m[3];  // row by=1
+  out[0] = -p0 - q0 - A - B + cm * (T(2) * r00 + r10);
+  out[1] = p0 - q1 + A - B + cm * (T(2) * r01 + r11);
+  out[2] = -p1 + q0 - A + B + cm * (T(2) * r10 + r00);
+  out[3] = p1 + q1 + A + B + cm * (T(2) * r11 + r01);
+}
+
+// 1D factor [[2,1],[1,2]] along one axis of a 2x2x2 block given by index stride
+template <typename T>
+__device__ __forceinline__ void m1_axis(T (&f)[8], int stride) {
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    if (v & stride) continue;
+    const T a = f[v], b = f[v + stride];
+    f[v] = T(2) * a + b;
+    f[v + stride] = a + T(2) * b;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void elem_apply_3d(const T (&k)[8], const T (&m)[8], const Tensor3<T>& D, T cxx, T cyy,
+                                              T czz, T cxy, T cm, T (&out)[8]) {
+  T fx[8], fy[8], fz[8], fm[8], gxy[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    // s_a (f1 - f0) along each axis
+    const int bx = v & 1, by = (v >> 1) & 1, bz = (v >> 2) & 1;
+    const T dxv = k[v | 1] - k[v & ~1];
+    const T dyv = k[v | 2] - k[v & ~2];
+    const T dzv = k[v | 4] - k[v & ~4];
+    fx[v] = bx ? dxv : -dxv;
+    fy[v] = by ? dyv : -dyv;
+    fz[v] = bz ? dzv : -dzv;
+    fm[v] = m[v];
+  }
+  // xy coupling: s_vx (h_y(0) + h_y(1)) + s_vy (h_x(0) + h_x(1)), h = differences
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int bx = v & 1, by = (v >> 1) & 1;
+    const int base = v & 4;  // same z layer
+    const T hy = (k[base | 2] - k[base]) + (k[base | 3] - k[base | 1]);
+    const T hx = (k[base | 1] - k[base]) + (k[base | 3] - k[base | 2]);
+    gxy[v] = (bx ? hy : -hy) + (by ? hx : -hx);
+  }
+  m1_axis(fx, 2); m1_axis(fx, 4);
+  m1_axis(fy, 1); m1_axis(fy, 4);
+  m1_axis(fz, 1); m1_axis(fz, 2);
+  m1_axis(gxy, 4);
+  m1_axis(fm, 1); m1_axis(fm, 2); m1_axis(fm, 4);
+  const T ax = D.xx * cxx, ay = D.yy * cyy, az = D.zz * czz, axy = D.xy * cxy;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) out[v] = ax * fx[v] + ay * fy[v] + az * fz[v] + axy * gxy[v] + cm * fm[v];
+}
+
+}  // namespace stm

@@ -1,4 +1,4 @@
-// Fused space-time solver: one workgroup (a "team") owns one sample at a time
+// Fused space-time solver: a team of G workgroups owns one sample at a time
 // and runs its whole nonlinear space-time solve without leaving the kernel.
 //
 // Method (Sec. 3.3 eq. mono_disc, Sec. 3.5): the backward-Euler space-time
@@ -16,10 +16,17 @@
 // from already computed samples) or, without one, u_{k-1}.  The activation
 // map is updated as each slab is accepted.
 //
-// Memory: stencil passes on the level's own grid stage tiles of their two
-// nodal input fields and of the element conductivities into LDS with
-// coalesced independent loads, then compute from LDS; coarse multigrid grids
-// are read from global memory.
+// Teams: with G = 1 a workgroup owns the sample.  With G > 1 (single-grid
+// V-cycle only) member r owns node rows [r ny / G, (r+1) ny / G) of the grid;
+// passes end with a team barrier (agent-scope release/acquire around an
+// atomic counter, bounded wait) and reductions sum the members' partials in
+// rank order, so every member takes identical control-flow decisions.  Such
+// launches are cooperative: co-residency is guaranteed or the launch fails.
+//
+// Memory: stencil passes on the level's grid stage tiles of their nodal
+// fields and element conductivities into LDS with batched loads, compute each
+// element's vertex contributions once (sum factorisation) and gather them per
+// node; coarse multigrid grids are read from global memory.
 //
 // Precision: the residual R_k, the update u += delta, the activation
 // interpolation and every stored solution are float64.  The Krylov and
@@ -29,6 +36,20 @@
 #include "stm_launch.h"
 
 namespace stm {
+
+// Optional per-phase timers (development builds with -DSTM_PHASE_TIMERS):
+// thread 0 accumulates wall-clock ticks of each solver phase.
+#ifdef STM_PHASE_TIMERS
+#define STM_T0(v) long long v = wall_clock64()
+#define STM_T1(v, slot) \
+  if (threadIdx.x == 0) ph_acc[slot] += wall_clock64() - v
+#else
+#define STM_T0(v)
+#define STM_T1(v, slot)
+#endif
+
+constexpr int kPartStride = 16;       // doubles per member in the partials buffer
+constexpr unsigned kSpinLimit = 1u << 25;
 
 template <int DIM>
 __device__ __forceinline__ void decode(const GridDev& g, int idx, int& i, int& j, int& k) {
@@ -101,10 +122,21 @@ struct Team {
   int64_t vstride;
   unsigned char* work;
   unsigned char* smem;   // dynamic LDS staging area
+  TI* kdiag0;            // diagonal of the stiffness matrix on grid 0 (per sample)
   double* omega;         // shared: per grid, the sweep weights [kMaxMG][kMaxSweeps]
+  double* red;           // shared: block reduction scratch
+  // team membership
+  int rank, G;
+  int jb0, jb1;          // owned node rows of grid 0
+  unsigned* bar;
+  double* part;
+  int* fault;
+  mutable unsigned gen;  // barriers passed
+  mutable unsigned rslot;  // reductions done (partials double buffer)
+  mutable bool broken;   // a barrier wait timed out: stop waiting
   // Algorithmic bytes of the passes run so far: every array a pass reads or
   // writes counted once per pass (neighbour and halo re-reads are cache/LDS
-  // traffic, not counted).  Uniform across the block; thread 0 reports it.
+  // traffic, not counted).  Uniform across the team; rank 0 reports it.
   mutable double bytes;
 
   __device__ __forceinline__ double dbytes(int l) const {
@@ -116,13 +148,102 @@ struct Team {
   __device__ TI* mgW(int l) const { return reinterpret_cast<TI*>(work + L->off_mgW[l]); }
   __device__ TI* mgD(int l) const { return reinterpret_cast<TI*>(work + L->off_mgD[l]); }
 
+  // ---- team synchronisation and reductions --------------------------------
+  // Every wave first waits until its own global stores have completed (a
+  // workgroup barrier alone does not wait for them); thread 0 then releases
+  // the block's writes at agent scope (write-back of the L2), arrives, waits
+  // for the other members and acquires, which invalidates the CU's caches for
+  // every wave of the block.
+  __device__ void team_barrier() const {
+    if (G > 1) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (G > 1) {
+      if (threadIdx.x == 0) {
+        gen += 1;
+        if (!broken) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned target = gen * (unsigned)G;
+          unsigned spins = 0;
+          while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+              broken = true;
+              __hip_atomic_store(fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // End of a pass whose results other members read.
+  __device__ __forceinline__ void sync() const { team_barrier(); }
+
+  template <int NV>
+  __device__ void tsum(double (&v)[NV]) const {
+    block_sum<BLOCK, NV>(v, red);
+    if (G == 1) return;
+    double* slot = part + (size_t)(rslot & 1) * G * kPartStride;
+    rslot += 1;
+    if (threadIdx.x == 0)
+      for (int i = 0; i < NV; ++i)
+        __hip_atomic_store(slot + rank * kPartStride + i, v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    team_barrier();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0.0;
+      for (int r = 0; r < G; ++r)
+        s += __hip_atomic_load(slot + r * kPartStride + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v[i] = s;
+    }
+  }
+  __device__ double tmax(double v) const {
+    v = block_max<BLOCK>(v, red);
+    if (G == 1) return v;
+    double* slot = part + (size_t)(rslot & 1) * G * kPartStride;
+    rslot += 1;
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slot + rank * kPartStride, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    team_barrier();
+    double s = 0.0;
+    for (int r = 0; r < G; ++r)
+      s = fmax(s, __hip_atomic_load(slot + r * kPartStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    return s;
+  }
+
+  // ---- owned nodes of grid 0 ----------------------------------------------
+  __device__ __forceinline__ int nband() const {
+    const GridDev& g = L->g[0];
+    return (jb1 - jb0) * g.nx * ((DIM == 3) ? g.nz : 1);
+  }
+  __device__ __forceinline__ int bidx(int q) const {
+    const GridDev& g = L->g[0];
+    if constexpr (DIM == 2) {
+      return jb0 * g.nx + q;
+    } else {
+      const int w = (jb1 - jb0) * g.nx;
+      const int kk = q / w;
+      return (kk * g.ny + jb0) * g.nx + (q - kk * w);
+    }
+  }
+
   // ---- staged pass on grid 0 ----------------------------------------------
-  // Stages fields fa, fb (type T) and the element conductivities of each tile
-  // into LDS, then calls body(i, j, k, idx, A, B, S) for every node of the
-  // tile; A(ii, jj, kk), B(...) read the staged fields, S(ex, ey, ez) the
-  // element tensor.  Ends with a barrier.
-  template <typename T, typename Body>
-  __device__ void staged(const T* __restrict__ fa, const T* __restrict__ fb, Body body) const {
+  // For each tile of the owned rows: stage nodal fields f0, f1 (with a
+  // one-node halo), f2, f3 (optional, may be null) and the tile's element
+  // conductivities into LDS, every thread issuing all of its loads before
+  // using any; compute every element's vertex contributions of
+  // M mval + K kval once (phase A, kval/mval from the raw f0, f1 values); sum
+  // the adjacent elements' contributions per node (phase B) and call
+  // body(idx, i, j, k, y, o0, o1, o2, o3) with o* the staged values at the
+  // node.  Phases A and B read LDS only.  Ends with a team barrier.
+  template <typename T, typename KV, typename MV, typename Body>
+  __device__ void staged(const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
+                         const T* __restrict__ f3, KV kval, MV mval, Body body) const {
+    constexpr int NV = (DIM == 3) ? 8 : 4;
+    constexpr int U = 4;
     const GridDev& g = L->g[0];
     const int nx = g.nx;
     const int Ry = sizeof(T) == 8 ? L->tile_y8 : L->tile_y4;
@@ -131,49 +252,140 @@ struct Team {
     const double* __restrict__ sg = sigma;
     const double* __restrict__ fib = L->fib;
     const double tau = prm.tau;
+    const T hx = T(g.hx), hy = T(g.hy), hz = T(g.hz);
+    const T cxx = (DIM == 3) ? hy * hz / (T(36) * hx) : hy / (T(6) * hx);
+    const T cyy = (DIM == 3) ? hx * hz / (T(36) * hy) : hx / (T(6) * hy);
+    const T czz = hx * hy / (T(36) * hz), cxy = hz / T(24);
+    const T cm = (DIM == 3) ? hx * hy * hz / T(216) : hx * hy / T(36);
+    const int nf = 2 + (f2 ? 1 : 0) + (f3 ? 1 : 0);
     for (int k0 = 0; k0 < nzz; k0 += Rz) {
-      for (int j0 = 0; j0 < g.ny; j0 += Ry) {
-        const int jr0 = max(j0 - 1, 0), jr1 = min(j0 + Ry, g.ny - 1);
+      for (int j0 = jb0; j0 < jb1; j0 += Ry) {
+        const int je = min(j0 + Ry, jb1);  // computed rows [j0, je)
+        const int jr0 = max(j0 - 1, 0), jr1 = min(je, g.ny - 1);
         const int kr0 = (DIM == 3) ? max(k0 - 1, 0) : 0, kr1 = (DIM == 3) ? min(k0 + Rz, g.nz - 1) : 0;
         const int sy = jr1 - jr0 + 1;
         const int nst = sy * (kr1 - kr0 + 1) * nx;
-        T* la = reinterpret_cast<T*>(smem);
-        T* lb = la + nst;
-        double* ls = reinterpret_cast<double*>(smem + ((2 * nst * sizeof(T) + 15) & ~(size_t)15));
-        for (int q = threadIdx.x; q < nst; q += BLOCK) {
-          const int i = q % nx, r = q / nx;
-          const int jj = jr0 + r % sy, kk = kr0 + r / sy;
-          const int gq = (DIM == 3) ? ((kk * g.ny + jj) * nx + i) : (jj * nx + i);
-          la[q] = fa[gq];
-          lb[q] = fb[gq];
-        }
-        const int ey0 = max(j0 - 1, 0), ey1 = min(j0 + Ry - 1, g.ey - 1);
+        const int ey0 = max(j0 - 1, 0), ey1 = min(je - 1, g.ey - 1);
         const int ez0 = (DIM == 3) ? max(k0 - 1, 0) : 0, ez1 = (DIM == 3) ? min(k0 + Rz - 1, g.ez - 1) : 0;
         const int sey = ey1 - ey0 + 1;
         const int nse = sey * (ez1 - ez0 + 1) * g.ex;
+        T* l0 = reinterpret_cast<T*>(smem);
+        T* l1 = l0 + nst;
+        T* l2 = l1 + nst;
+        T* l3 = l2 + (f2 ? nst : 0);
+        double* ls = reinterpret_cast<double*>(smem + ((nf * (size_t)nst * sizeof(T) + 15) & ~(size_t)15));
+        T* lc = reinterpret_cast<T*>(ls + nse);
+        // ---- stage: batched loads, then LDS stores ----
+        for (int qb = threadIdx.x; qb < nst; qb += BLOCK * U) {
+          T r0[U], r1[U], r2[U], r3[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nst) {
+              const int i = q % nx, r = q / nx;
+              const int jj = jr0 + r % sy, kk = kr0 + r / sy;
+              const int gq = (DIM == 3) ? ((kk * g.ny + jj) * nx + i) : (jj * nx + i);
+              r0[u] = f0[gq];
+              r1[u] = f1[gq];
+              if (f2) r2[u] = f2[gq];
+              if (f3) r3[u] = f3[gq];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nst) {
+              l0[q] = r0[u];
+              l1[q] = r1[u];
+              if (f2) l2[q] = r2[u];
+              if (f3) l3[q] = r3[u];
+            }
+          }
+        }
+        for (int qb = threadIdx.x; qb < nse; qb += BLOCK * U) {
+          double rs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nse) {
+              const int ex = q % g.ex, r = q / g.ex;
+              const int ey = ey0 + r % sey, ez = ez0 + r / sey;
+              rs[u] = sg[(DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex)];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nse) ls[q] = rs[u];
+          }
+        }
+        __syncthreads();
+        // ---- phase A: element contributions ----
         for (int q = threadIdx.x; q < nse; q += BLOCK) {
           const int ex = q % g.ex, r = q / g.ex;
           const int ey = ey0 + r % sey, ez = ez0 + r / sey;
-          ls[q] = sg[(DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex)];
+          const auto D = tensor_from<T, DIM>(ls[q], fib + 3 * ((DIM == 3) ? ez : ey), tau);
+          const int base = ((ez - kr0) * sy + (ey - jr0)) * nx + ex;
+          T kv[NV], mv[NV], out[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int o = base + ((v >> 2) & 1) * sy * nx + ((v >> 1) & 1) * nx + (v & 1);
+            const T a = l0[o], b = l1[o];
+            kv[v] = kval(a, b);
+            mv[v] = mval(a, b);
+          }
+          if constexpr (DIM == 3) elem_apply_3d<T>(kv, mv, D, cxx, cyy, czz, cxy, cm, out);
+          else elem_apply_2d<T>(kv, mv, D, cxx, cyy, cm, out);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) lc[q * NV + v] = out[v];
         }
         __syncthreads();
-        auto A = [&](int ii, int jj, int kk) { return la[((kk - kr0) * sy + (jj - jr0)) * nx + ii]; };
-        auto B = [&](int ii, int jj, int kk) { return lb[((kk - kr0) * sy + (jj - jr0)) * nx + ii]; };
-        auto S = [&](int ex, int ey, int ez) {
-          const double s = ls[((ez - ez0) * sey + (ey - ey0)) * g.ex + ex];
-          return tensor_from<T, DIM>(s, fib + 3 * ((DIM == 3) ? ez : ey), tau);
-        };
-        const int cy = min(j0 + Ry, g.ny) - j0, cz = min(k0 + Rz, nzz) - k0;
+        // ---- phase B: nodes of the tile ----
+        const int cy = je - j0, cz = min(k0 + Rz, nzz) - k0;
         const int nc = cy * cz * nx;
         for (int q = threadIdx.x; q < nc; q += BLOCK) {
           const int i = q % nx, r = q / nx;
           const int j = j0 + r % cy, k = k0 + r / cy;
           const int idx = (DIM == 3) ? ((k * g.ny + j) * nx + i) : (j * nx + i);
-          body(i, j, k, idx, A, B, S);
+          T y = T(0);
+#pragma unroll
+          for (int c = 0; c < ((DIM == 3) ? 2 : 1); ++c) {
+            const int ez = k - 1 + c;
+            if (DIM == 3 && (ez < 0 || ez >= g.ez)) continue;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int ey = j - 1 + b;
+              if (ey < 0 || ey >= g.ey) continue;
+#pragma unroll
+              for (int a = 0; a < 2; ++a) {
+                const int ex = i - 1 + a;
+                if (ex < 0 || ex >= g.ex) continue;
+                const int el = (((DIM == 3) ? (ez - ez0) : 0) * sey + (ey - ey0)) * g.ex + ex;
+                const int v = (1 - a) + 2 * (1 - b) + ((DIM == 3) ? 4 * (1 - c) : 0);
+                y += lc[el * NV + v];
+              }
+            }
+          }
+          const int o = (((DIM == 3) ? (k - kr0) : 0) * sy + (j - jr0)) * nx + i;
+          body(idx, i, j, k, y, l0[o], l1[o], f2 ? l2[o] : T(0), f3 ? l3[o] : T(0));
         }
         __syncthreads();
       }
     }
+    if (G > 1) team_barrier();
+  }
+
+  // number of elements adjacent to node (i, j, k) of grid 0
+  __device__ __forceinline__ int nel0(int i, int j, int k) const {
+    const GridDev& g = L->g[0];
+    int c = ((i > 0) + (i < g.nx - 1)) * ((j > 0) + (j < g.ny - 1));
+    if constexpr (DIM == 3) c *= (k > 0) + (k < g.nz - 1);
+    return c;
+  }
+  // mass diagonal per adjacent element (times the nodal weight)
+  __device__ __forceinline__ TI cmd0() const {
+    const GridDev& g = L->g[0];
+    return (DIM == 3) ? TI(8.0 * g.hx * g.hy * g.hz / 216.0) : TI(4.0 * g.hx * g.hy / 36.0);
   }
 
   // y = A_l x at node idx of a coarse grid l >= 1 (global memory)
@@ -190,29 +402,17 @@ struct Team {
                              diag);
   }
 
-  // diagonal of A_l at node idx (any grid; global memory)
-  __device__ __forceinline__ TI diag_at(int l, int idx) const {
+  // diagonal of A_l at node idx of a coarse grid (global memory)
+  __device__ __forceinline__ TI diag_coarse(int l, int idx) const {
     const GridDev& g = L->g[l];
     const TI* __restrict__ w = mgW(l);
+    const TI* __restrict__ D = mgD(l);
     int i, j, k;
     decode<DIM>(g, idx, i, j, k);
     TI d;
     auto z = [&](int, int, int) { return TI(0); };
-    if (l == 0) {
-      const double* __restrict__ sg = sigma;
-      const double* __restrict__ fib = L->fib;
-      const double tau = prm.tau;
-      apply_at<TI, DIM>(g, i, j, k, z, z,
-                        [&](int ex, int ey, int ez) {
-                          const int e = (DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex);
-                          return tensor_from<TI, DIM>(sg[e], fib + 3 * ((DIM == 3) ? ez : ey), tau);
-                        },
-                        w[idx], &d);
-    } else {
-      const TI* __restrict__ D = mgD(l);
-      apply_at<TI, DIM>(g, i, j, k, z, z, [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); },
-                        w[idx], &d);
-    }
+    apply_at<TI, DIM>(g, i, j, k, z, z, [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); },
+                      w[idx], &d);
     return d;
   }
 
@@ -221,26 +421,54 @@ struct Team {
   __device__ void jacobi(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out,
                          TI om) const {
     const int n = L->g[l].n;
-    bytes += (x ? 4.0 : 3.0) * sizeof(TI) * n + dbytes(l);
-    if (!x) {
-      for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = om * b[idx] / diag_at(l, idx);
-      __syncthreads();
-      return;
-    }
+    bytes += (x ? 5.0 : 4.0) * sizeof(TI) * n + (x ? dbytes(l) : 0.0);
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
-      staged<TI>(x, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
-        TI d;
-        const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
-                                        A, S, B(i, j, k), &d);
-        out[idx] = A(i, j, k) + om * (b[idx] - ax) / d;
-      });
+      const TI cmd = cmd0();
+      if (!x) {
+        const int nb = nband();
+        for (int qb = threadIdx.x; qb < nb; qb += BLOCK * 4) {
+          TI rb[4], rk[4], rw[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = qb + v * BLOCK;
+            if (q < nb) {
+              const int idx = bidx(q);
+              rb[v] = b[idx];
+              rk[v] = kdiag0[idx];
+              rw[v] = w[idx];
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = qb + v * BLOCK;
+            if (q < nb) {
+              const int idx = bidx(q);
+              int i, j, k;
+              decode<DIM>(L->g[0], idx, i, j, k);
+              out[idx] = om * rb[v] / (rk[v] + TI(nel0(i, j, k)) * cmd * rw[v]);
+            }
+          }
+        }
+        sync();
+        return;
+      }
+      staged<TI>(
+          x, w, b, kdiag0, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+          [&](int idx, int i, int j, int k, TI y, TI xo, TI wo, TI bo, TI kdo) {
+            const TI d = kdo + TI(nel0(i, j, k)) * cmd * wo;
+            out[idx] = xo + om * (bo - y) / d;
+          });
       return;
     }
-    for (int idx = threadIdx.x; idx < n; idx += BLOCK) {
-      TI d;
-      const TI ax = apply_coarse(l, x, idx, &d);
-      out[idx] = x[idx] + om * (b[idx] - ax) / d;
+    if (!x) {
+      for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = om * b[idx] / diag_coarse(l, idx);
+    } else {
+      for (int idx = threadIdx.x; idx < n; idx += BLOCK) {
+        TI d;
+        const TI ax = apply_coarse(l, x, idx, &d);
+        out[idx] = x[idx] + om * (b[idx] - ax) / d;
+      }
     }
     __syncthreads();
   }
@@ -250,18 +478,16 @@ struct Team {
     bytes += 4.0 * sizeof(TI) * n + dbytes(l);
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
-      staged<TI>(x, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
-        const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
-                                        A, S, TI(0), (TI*)nullptr);
-        out[idx] = b[idx] - ax;
-      });
+      staged<TI>(
+          x, w, b, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+          [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
       return;
     }
     for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = b[idx] - apply_coarse(l, x, idx, nullptr);
     __syncthreads();
   }
 
-  // coarse[l+1] = P^T fine[l]  (full weighting, transpose of Q1 interpolation)
+  // coarse[l+1] = P^T fine[l]  (full weighting, transpose of Q1 interpolation); G == 1 only
   __device__ void restrict_to(int l, const TI* __restrict__ rf, TI* __restrict__ bc) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
@@ -294,7 +520,7 @@ struct Team {
     __syncthreads();
   }
 
-  // fine[l] += P coarse[l+1]  (Q1 interpolation of nested grids)
+  // fine[l] += P coarse[l+1]  (Q1 interpolation of nested grids); G == 1 only
   __device__ void prolong_add(int l, const TI* __restrict__ xc, TI* __restrict__ xf) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
@@ -353,29 +579,36 @@ struct Team {
   }
 
   // lmax of D^-1 A_l by power iteration from a smooth + checkerboard start.
-  // Uses buffers x0, x1 of grid l.  Returns the estimate (block-uniform).
-  __device__ double power_lmax(int l, TI* x0, TI* x1, double* red) const {
+  // Uses buffers x0, x1 of grid l.  Returns the estimate (team-uniform).
+  __device__ double power_lmax(int l, TI* x0, TI* x1) const {
     const GridDev& g = L->g[l];
-    for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
+    auto init = [&](int idx) {
       int i, j, k;
       decode<DIM>(g, idx, i, j, k);
       x0[idx] = TI(1.0 + 0.5 * (((i + j + k) & 1) ? -1.0 : 1.0));
+    };
+    if (l == 0) {
+      for (int q = threadIdx.x; q < nband(); q += BLOCK) init(bidx(q));
+      sync();
+    } else {
+      for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) init(idx);
+      __syncthreads();
     }
-    __syncthreads();
     double lam = 0.0;
     for (int it = 0; it < prm.power_iters; ++it) {
       double nn[2] = {0.0, 0.0};
       if (l == 0) {
         const TI* __restrict__ w = mgW(0);
-        staged<TI>(x0, w, [&](int i, int j, int k, int idx, auto& A, auto& B, auto& S) {
-          TI d;
-          const TI ax = apply_at<TI, DIM>(L->g[0], i, j, k, [&](int a, int bb, int c) { return B(a, bb, c) * A(a, bb, c); },
-                                          A, S, B(i, j, k), &d);
-          const TI y = ax / d;
-          x1[idx] = y;
-          nn[0] += double(y) * double(y);
-          nn[1] += double(A(i, j, k)) * double(A(i, j, k));
-        });
+        const TI cmd = cmd0();
+        staged<TI>(
+            x0, w, kdiag0, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+            [&](int idx, int i, int j, int k, TI ax, TI xown, TI wo, TI kdo, TI) {
+              const TI d = kdo + TI(nel0(i, j, k)) * cmd * wo;
+              const TI y = ax / d;
+              x1[idx] = y;
+              nn[0] += double(y) * double(y);
+              nn[1] += double(xown) * double(xown);
+            });
       } else {
         for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
           TI d;
@@ -386,11 +619,19 @@ struct Team {
           nn[1] += double(x0[idx]) * double(x0[idx]);
         }
       }
-      block_sum<BLOCK, 2>(nn, red);
+      tsum<2>(nn);
       lam = sqrt(nn[0] / nn[1]);
       const TI scl = TI(1.0 / sqrt(nn[0]));
-      for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) x0[idx] = x1[idx] * scl;
-      __syncthreads();
+      if (l == 0) {
+        for (int q = threadIdx.x; q < nband(); q += BLOCK) {
+          const int idx = bidx(q);
+          x0[idx] = x1[idx] * scl;
+        }
+        sync();
+      } else {
+        for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) x0[idx] = x1[idx] * scl;
+        __syncthreads();
+      }
     }
     bytes += prm.power_iters * (5.0 * sizeof(TI) * g.n + dbytes(l));
     return lam;
@@ -420,6 +661,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   __shared__ double yv[kMaxRestart], coef[kMaxRestart + 1];
   __shared__ double omega_tab[kMaxMG * kMaxSweeps];
   __shared__ double sh_resid;
+#ifdef STM_PHASE_TIMERS
+  long long ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#endif
 
   const TeamTask task = tasks[blockIdx.x];
   const LevelDev* L = levels + task.level;
@@ -431,14 +675,27 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   tm.work = task.work;
   tm.smem = smem_dyn;
   tm.omega = omega_tab;
+  tm.red = red;
   tm.bytes = 0.0;
+  tm.rank = task.rank;
+  tm.G = task.G;
+  tm.bar = task.bar;
+  tm.part = task.part;
+  tm.fault = task.fault;
+  tm.gen = 0;
+  tm.rslot = 0;
+  tm.broken = false;
   const GridDev g0 = L->g[0];
+  tm.jb0 = (int)((long long)task.rank * g0.ny / task.G);
+  tm.jb1 = (int)((long long)(task.rank + 1) * g0.ny / task.G);
   const int n0 = g0.n;
+  const int nb = tm.nband();
   double* __restrict__ u = reinterpret_cast<double*>(task.work + L->off_u);
   double* __restrict__ uprev = reinterpret_cast<double*>(task.work + L->off_uprev);
   double* __restrict__ wk1 = reinterpret_cast<double*>(task.work + L->off_wk1);
   double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
   tm.V = reinterpret_cast<TI*>(task.work + L->off_V);
+  tm.kdiag0 = reinterpret_cast<TI*>(task.work + L->off_kd);
   tm.Z = reinterpret_cast<TI*>(task.work + L->off_Z);
   const int64_t vs = (int64_t)((n0 + 63) & ~63);
   tm.vstride = vs;
@@ -462,27 +719,27 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     if (task.u_guess) W = task.u_guess + (int64_t)s * m * n0;
     else if (have_prev) W = prevU;
 
-    // ---- per-sample setup: coarse element tensors (averages of children) ----
+    // ---- per-sample setup: coarse element tensors (averages of children; G == 1) ----
     for (int l = 1; l < L->nmg; ++l) {
       const GridDev& gc = L->g[l];
       const GridDev& gf = L->g[l - 1];
       TI* Dc = tm.mgD(l);
       const TI* Df = tm.mgD(l - 1);
       for (int e = tid; e < gc.ne; e += BLOCK) {
-        int E = e % gc.ex, F, G;
+        int E = e % gc.ex, F, Gz;
         if constexpr (DIM == 2) {
           F = e / gc.ex;
-          G = 0;
+          Gz = 0;
         } else {
           F = (e / gc.ex) % gc.ey;
-          G = e / (gc.ex * gc.ey);
+          Gz = e / (gc.ex * gc.ey);
         }
         double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
         const int cz = (DIM == 3) ? 2 : 1;
         for (int c = 0; c < cz; ++c)
           for (int b = 0; b < 2; ++b)
             for (int a = 0; a < 2; ++a) {
-              const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * G + c;
+              const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * Gz + c;
               const int fe = (DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx);
               if (l == 1) {
                 auto D = tensor_from<double, DIM>(tm.sigma[fe], L->fib + 3 * ((DIM == 3) ? fz : fy), tau);
@@ -505,17 +762,30 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       }
       __syncthreads();
     }
+    // diagonal of the stiffness matrix on grid 0 (sigma is fixed for the sample),
     // initial state, activation markers, warm-start history
-    for (int idx = tid; idx < n0; idx += BLOCK) {
+    tm.bytes += (16.0 + sizeof(TI) + 24.0) * n0;
+    for (int q = tid; q < nb; q += BLOCK) {
+      const int idx = tm.bidx(q);
       int i, j, k;
       decode<DIM>(g0, idx, i, j, k);
-      const double x = i * g0.hx - L->ic_cx, y = j * g0.hy - L->ic_cy, z = (DIM == 3) ? (k * g0.hz - L->ic_cz) : 0.0;
-      const double v = (x * x + y * y + z * z <= L->ic_r2) ? 1.0 : 0.0;
+      auto z = [&](int, int, int) { return 0.0; };
+      double dd;
+      apply_at<double, DIM>(
+          g0, i, j, k, z, z,
+          [&](int ex, int ey, int ez) {
+            const int e = (DIM == 3) ? ((ez * g0.ey + ey) * g0.ex + ex) : (ey * g0.ex + ex);
+            return tensor_from<double, DIM>(tm.sigma[e], L->fib + 3 * ((DIM == 3) ? ez : ey), tau);
+          },
+          0.0, &dd);
+      tm.kdiag0[idx] = TI(dd);
+      const double x = i * g0.hx - L->ic_cx, y = j * g0.hy - L->ic_cy, zc = (DIM == 3) ? (k * g0.hz - L->ic_cz) : 0.0;
+      const double v = (x * x + y * y + zc * zc <= L->ic_r2) ? 1.0 : 0.0;
       uprev[idx] = v;
       wk1[idx] = v;
       tact[idx] = (v >= thr) ? 0.0 : -1.0;
     }
-    __syncthreads();
+    tm.sync();
 
     long long newton_total = 0, krylov_total = 0;
     int newton_max_slab = 0, status = 0;
@@ -526,7 +796,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       // ---- initial iterate of slab k ----
       const double* Wk = W ? W + (int64_t)k * n0 : nullptr;
       tm.bytes += (Wk ? 40.0 : 16.0) * n0;
-      for (int idx = tid; idx < n0; idx += BLOCK) {
+      for (int q = tid; q < nb; q += BLOCK) {
+        const int idx = tm.bidx(q);
         if (Wk) {
           const double w = Wk[idx];
           u[idx] = uprev[idx] + (w - wk1[idx]);
@@ -535,9 +806,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           u[idx] = uprev[idx];
         }
       }
-      __syncthreads();
+      tm.sync();
 
-      double dprev = 0.0, eta = fmax(prm.gmres_rtol, 1e-4);
+      double dprev = 0.0, eta = fmax(prm.gmres_rtol, 1e-5);
       int it = 0;
       bool conv = false;
       double dmax = 0.0;
@@ -546,22 +817,19 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         TI* V0 = tm.V;
         TI* w0 = tm.mgW(0);
         double rr[1] = {0.0};
+        STM_T0(t_res);
         tm.bytes += 16.0 * n0 + 8.0 * g0.ne + 2.0 * sizeof(TI) * n0;
         for (int l = 1; l < L->nmg; ++l) tm.bytes += (8.0 + sizeof(TI)) * L->g[l].n;
-        tm.template staged<double>(u, uprev, [&](int i, int j, int kk, int idx, auto& A, auto& B, auto& S) {
-          const double y = apply_at<double, DIM>(
-              g0, i, j, kk,
-              [&](int a, int b, int c) {
-                const double uq = A(a, b, c);
-                return (uq - B(a, b, c)) * inv_dt - react(uq, kr, ar);
-              },
-              A, S, 0.0, (double*)nullptr);
-          const double r = -y;
-          V0[idx] = TI(r);
-          w0[idx] = TI(inv_dt - react_d(A(i, j, kk), kr, ar));
-          rr[0] += r * r;
-        });
-        for (int l = 1; l < L->nmg; ++l) {
+        tm.template staged<double>(
+            u, uprev, (const double*)nullptr, (const double*)nullptr, [](double a, double) { return a; },
+            [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
+            [&](int idx, int, int, int, double y, double uown, double, double, double) {
+              const double r = -y;
+              V0[idx] = TI(r);
+              w0[idx] = TI(inv_dt - react_d(uown, kr, ar));
+              rr[0] += r * r;
+            });
+        for (int l = 1; l < L->nmg; ++l) {  // G == 1 here
           const GridDev& gc = L->g[l];
           TI* wl = tm.mgW(l);
           const int st = 1 << l;
@@ -572,7 +840,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             wl[idx] = TI(inv_dt - react_d(u[q], kr, ar));
           }
         }
-        block_sum<BLOCK, 1>(rr, red);  // its barriers also publish the writes above
+        tm.template tsum<1>(rr);  // its barriers also publish the writes above
+        STM_T1(t_res, 0);
         const double beta = sqrt(rr[0]);
         if (!isfinite(beta)) {
           status = -5;
@@ -588,7 +857,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           for (int l = 0; l < L->nmg; ++l) {
             TI* x0 = (l == 0) ? tm.V + vs : tm.mgX(l);
             TI* x1 = (l == 0) ? tm.V + 2 * vs : tm.mgT(l);
-            const double lmax = 1.05 * tm.power_lmax(l, x0, x1, red);
+            const double lmax = 1.05 * tm.power_lmax(l, x0, x1);
             const int K = (l == L->nmg - 1) ? prm.coarse_sweeps : prm.smooth_steps;
             if (tid == 0) chebyshev_weights(lmax / prm.cheb_ratio, lmax, K, omega_tab + l * kMaxSweeps);
           }
@@ -608,26 +877,44 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           TI* Vj = tm.V + j * vs;
           TI* Zj = tm.Z + j * vs;
           TI* Vn = tm.V + (j + 1) * vs;
+          STM_T0(t_vc);
           tm.vcycle(Vj, Zj);
-          // pass A: ws = A Z_j (into V_{j+1}), dots with V_0..V_min(j,7)
+          STM_T1(t_vc, 1);
+          STM_T0(t_pa);
+          // pass A: ws = A Z_j (into V_{j+1})
+          tm.bytes += 3.0 * sizeof(TI) * n0 + tm.dbytes(0);
+          tm.template staged<TI>(
+              Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [](TI a, TI) { return a; },
+              [](TI a, TI ww) { return ww * a; },
+              [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { Vn[idx] = w; });
+          STM_T1(t_pa, 2);
+          STM_T0(t_dot);
+          // dots with V_0..V_min(j,7) over the owned nodes: batched loads
           double d[9];
 #pragma unroll
           for (int q = 0; q < 9; ++q) d[q] = 0.0;
           const int nk0 = min(j + 1, 8);
-          tm.bytes += (3.0 + nk0) * sizeof(TI) * n0 + tm.dbytes(0);
+          tm.bytes += (1.0 + nk0) * sizeof(TI) * n0;
           {
             const TI* __restrict__ Vb = tm.V;
-            tm.template staged<TI>(Zj, tm.mgW(0), [&](int i, int jj, int kk, int idx, auto& A, auto& B, auto& S) {
-              const TI w = apply_at<TI, DIM>(g0, i, jj, kk, [&](int a, int b, int c) { return B(a, b, c) * A(a, b, c); },
-                                             A, S, TI(0), (TI*)nullptr);
-              Vn[idx] = w;
-              const double wd = double(w);
+            const TI* __restrict__ Vr = Vn;
+            for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+              TI wv[2], vv[2][8];
 #pragma unroll
-              for (int q = 0; q < 8; ++q)
-                if (q < nk0) d[q] += double(Vb[q * vs + idx]) * wd;
-            });
+              for (int uu = 0; uu < 2; ++uu) {
+                const int q = qb + uu * BLOCK;
+                const int idx = q < nb ? tm.bidx(q) : 0;
+                wv[uu] = q < nb ? Vr[idx] : TI(0);
+#pragma unroll
+                for (int p = 0; p < 8; ++p) vv[uu][p] = (p < nk0 && q < nb) ? Vb[p * vs + idx] : TI(0);
+              }
+#pragma unroll
+              for (int uu = 0; uu < 2; ++uu)
+#pragma unroll
+                for (int p = 0; p < 8; ++p) d[p] += double(vv[uu][p]) * double(wv[uu]);
+            }
           }
-          block_sum<BLOCK, 9>(d, red);
+          tm.template tsum<9>(d);
           if (tid == 0)
             for (int q = 0; q < nk0; ++q) H[q * kMaxRestart + j] = sc[q] * sc[j] * d[q];
           for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
@@ -635,30 +922,51 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             tm.bytes += (1.0 + nk) * sizeof(TI) * n0;
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0;
-            for (int idx = tid; idx < n0; idx += BLOCK) {
+            for (int q = tid; q < nb; q += BLOCK) {
+              const int idx = tm.bidx(q);
               const double wd = double(Vn[idx]);
 #pragma unroll
-              for (int q = 0; q < 8; ++q)
-                if (q < nk) d[q] += double(tm.V[(k0 + q) * vs + idx]) * wd;
+              for (int p = 0; p < 8; ++p)
+                if (p < nk) d[p] += double(tm.V[(k0 + p) * vs + idx]) * wd;
             }
-            block_sum<BLOCK, 9>(d, red);
+            tm.template tsum<9>(d);
             if (tid == 0)
               for (int q = 0; q < nk; ++q) H[(k0 + q) * kMaxRestart + j] = sc[k0 + q] * sc[j] * d[q];
           }
           if (tid == 0)
             for (int q = 0; q <= j; ++q) coef[q] = H[q * kMaxRestart + j] * sc[q] / sc[j];
           __syncthreads();
-          // pass B: V_{j+1} -= sum_q coef_q V_q ; norm
+          STM_T1(t_dot, 3);
+          STM_T0(t_pb);
+          // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
           double nn[1] = {0.0};
           tm.bytes += (j + 3.0) * sizeof(TI) * n0;
-          for (int idx = tid; idx < n0; idx += BLOCK) {
-            double w = double(Vn[idx]);
-            for (int q = 0; q <= j; ++q) w -= coef[q] * double(tm.V[q * vs + idx]);
-            const TI wt = TI(w);
-            Vn[idx] = wt;
-            nn[0] += double(wt) * double(wt);
+          for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+            double w[2];
+            int ix[2];
+#pragma unroll
+            for (int uu = 0; uu < 2; ++uu) {
+              const int q = qb + uu * BLOCK;
+              ix[uu] = q < nb ? tm.bidx(q) : -1;
+              w[uu] = ix[uu] >= 0 ? double(Vn[ix[uu]]) : 0.0;
+            }
+            for (int q = 0; q <= j; ++q) {
+              const TI* __restrict__ Vq = tm.V + q * vs;
+              const double cq = coef[q];
+#pragma unroll
+              for (int uu = 0; uu < 2; ++uu)
+                if (ix[uu] >= 0) w[uu] -= cq * double(Vq[ix[uu]]);
+            }
+#pragma unroll
+            for (int uu = 0; uu < 2; ++uu) {
+              if (ix[uu] >= 0) {
+                const TI wt = TI(w[uu]);
+                Vn[ix[uu]] = wt;
+                nn[0] += double(wt) * double(wt);
+              }
+            }
           }
-          block_sum<BLOCK, 1>(nn, red);
+          tm.template tsum<1>(nn);
           const double hn = sqrt(nn[0]);
           if (tid == 0) {
             const double hj1 = sc[j] * hn;
@@ -680,6 +988,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             sh_resid = fabs(gv[j + 1]);
           }
           __syncthreads();
+          STM_T1(t_pb, 4);
           jdim = j + 1;
           const double resid = sh_resid;
           if (!(resid > tol_abs) || !(hn > 0.0)) break;
@@ -694,16 +1003,36 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           for (int q = 0; q < jdim; ++q) coef[q] = yv[q] * sc[q];
         }
         __syncthreads();
-        // ---- u += sum_q y_q z_q (float64), max-norm of the step ----
+        // ---- u += sum_q y_q z_q (float64) over the owned nodes, max-norm of the step ----
+        STM_T0(t_up);
         double dm = 0.0;
         tm.bytes += double(jdim) * sizeof(TI) * n0 + 16.0 * n0;
-        for (int idx = tid; idx < n0; idx += BLOCK) {
-          double dlt = 0.0;
-          for (int q = 0; q < jdim; ++q) dlt += coef[q] * double(tm.Z[q * vs + idx]);
-          u[idx] += dlt;
-          dm = fmax(dm, fabs(dlt));
+        for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+          double dlt[2] = {0.0, 0.0}, uo[2];
+          int ix[2];
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const int q = qb + v * BLOCK;
+            ix[v] = q < nb ? tm.bidx(q) : -1;
+            uo[v] = ix[v] >= 0 ? u[ix[v]] : 0.0;
+          }
+          for (int q = 0; q < jdim; ++q) {
+            const TI* __restrict__ Zq = tm.Z + q * vs;
+            const double cq = coef[q];
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+              if (ix[v] >= 0) dlt[v] += cq * double(Zq[ix[v]]);
+          }
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            if (ix[v] >= 0) {
+              u[ix[v]] = uo[v] + dlt[v];
+              dm = fmax(dm, fabs(dlt[v]));
+            }
+          }
         }
-        dmax = block_max<BLOCK>(dm, red);
+        dmax = tm.tmax(dm);  // its barrier also publishes u to the other members
+        STM_T1(t_up, 5);
         const double ach = sh_resid / beta;
         if (!isfinite(dmax)) {
           status = -5;
@@ -736,18 +1065,20 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       double* Uk = Uout + (int64_t)k * n0;
       const double tk = k * dt;
       tm.bytes += 40.0 * n0;
-      for (int idx = tid; idx < n0; idx += BLOCK) {
+      for (int q = tid; q < nb; q += BLOCK) {
+        const int idx = tm.bidx(q);
         const double un = u[idx], up = uprev[idx];
         Uk[idx] = un;
         if (tact[idx] < 0.0 && un >= thr) tact[idx] = tk + dt * (thr - up) / (un - up);
         uprev[idx] = un;
       }
-      __syncthreads();
+      tm.sync();
     }
 
     // ---- finalize the sample ----
     double cen[1] = {0.0};
-    for (int idx = tid; idx < n0; idx += BLOCK) {
+    for (int q = tid; q < nb; q += BLOCK) {
+      const int idx = tm.bidx(q);
       double t = tact[idx];
       if (t < 0.0) {
         t = L->T;
@@ -755,10 +1086,10 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       }
       if (task.t_act) task.t_act[(int64_t)s * n0 + idx] = t;
     }
-    block_sum<BLOCK, 1>(cen, red);
-    if (tid == 0 && task.stats) {
+    tm.template tsum<1>(cen);
+    if (tid == 0 && task.stats && task.rank == 0) {
       SampleStatsDev st;
-      st.status = status;
+      st.status = tm.broken ? -3 : status;
       st.newton_max_per_slab = newton_max_slab;
       st.newton_iters = newton_total;
       st.krylov_iters = krylov_total;
@@ -767,11 +1098,18 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       st.censored = (int)cen[0];
       st.pad = 0;
       st.alg_bytes = tm.bytes;
+      for (int q = 0; q < 8; ++q) st.phase_ticks[q] = 0;
+#ifdef STM_PHASE_TIMERS
+      for (int q = 0; q < 8; ++q) st.phase_ticks[q] = ph_acc[q];
+#endif
       task.stats[s] = st;
     }
+#ifdef STM_PHASE_TIMERS
+    for (int q = 0; q < 8; ++q) ph_acc[q] = 0;
+#endif
     prevU = Uout;
     have_prev = (status == 0);
-    __syncthreads();
+    tm.sync();
   }
 }
 
@@ -779,34 +1117,53 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
 // host launcher
 // ---------------------------------------------------------------------------
 template <typename TI, int DIM, int BLOCK>
-static hipError_t launch_one(const LevelDev* levels, const TeamTask* tasks, int n_tasks, SolverParams prm,
-                             size_t lds, hipStream_t st) {
+static hipError_t launch_one(const LevelDev* levels, const TeamTask* tasks, int n_blocks, SolverParams prm,
+                             size_t lds, bool cooperative, hipStream_t st) {
   auto kern = st_team_kernel<TI, DIM, BLOCK>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n_tasks), dim3(BLOCK), lds, st, levels, tasks, prm);
+  if (cooperative) {
+    void* args[] = {(void*)&levels, (void*)&tasks, (void*)&prm};
+    return hipLaunchCooperativeKernel((const void*)kern, dim3(n_blocks), dim3(BLOCK), args, (unsigned)lds, st);
+  }
+  hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(BLOCK), lds, st, levels, tasks, prm);
   return hipGetLastError();
 }
 
 template <typename TI, int DIM>
-static hipError_t launch_dim(const LevelDev* levels, const TeamTask* tasks, int n_tasks, SolverParams prm, int block,
-                             size_t lds, hipStream_t st) {
+static hipError_t launch_dim(const LevelDev* levels, const TeamTask* tasks, int n_blocks, SolverParams prm, int block,
+                             size_t lds, bool coop, hipStream_t st) {
   switch (block) {
-    case 256: return launch_one<TI, DIM, 256>(levels, tasks, n_tasks, prm, lds, st);
-    case 512: return launch_one<TI, DIM, 512>(levels, tasks, n_tasks, prm, lds, st);
-    case 1024: return launch_one<TI, DIM, 1024>(levels, tasks, n_tasks, prm, lds, st);
+    case 256: return launch_one<TI, DIM, 256>(levels, tasks, n_blocks, prm, lds, coop, st);
+    case 512: return launch_one<TI, DIM, 512>(levels, tasks, n_blocks, prm, lds, coop, st);
+    case 1024: return launch_one<TI, DIM, 1024>(levels, tasks, n_blocks, prm, lds, coop, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_tasks,
-                              SolverParams prm, int block, size_t lds_bytes, hipStream_t st) {
-  if (n_tasks <= 0) return hipSuccess;
+hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_blocks,
+                              SolverParams prm, int block, size_t lds_bytes, bool cooperative, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
   if (dim == 2)
-    return inner_fp32 ? launch_dim<float, 2>(levels, tasks, n_tasks, prm, block, lds_bytes, st)
-                      : launch_dim<double, 2>(levels, tasks, n_tasks, prm, block, lds_bytes, st);
-  return inner_fp32 ? launch_dim<float, 3>(levels, tasks, n_tasks, prm, block, lds_bytes, st)
-                    : launch_dim<double, 3>(levels, tasks, n_tasks, prm, block, lds_bytes, st);
+    return inner_fp32 ? launch_dim<float, 2>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st)
+                      : launch_dim<double, 2>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st);
+  return inner_fp32 ? launch_dim<float, 3>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st)
+                    : launch_dim<double, 3>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st);
+}
+
+// Co-resident workgroups per CU for a launch configuration (0 on error).
+int team_solver_occupancy(int dim, bool inner_fp32, int block, size_t lds_bytes) {
+  int nb = 0;
+  const void* f = nullptr;
+#define STM_OCC(TI, D, B) f = (const void*)st_team_kernel<TI, D, B>
+  if (dim == 2 && !inner_fp32) { if (block == 256) STM_OCC(double, 2, 256); else if (block == 512) STM_OCC(double, 2, 512); else STM_OCC(double, 2, 1024); }
+  if (dim == 2 && inner_fp32) { if (block == 256) STM_OCC(float, 2, 256); else if (block == 512) STM_OCC(float, 2, 512); else STM_OCC(float, 2, 1024); }
+  if (dim == 3 && !inner_fp32) { if (block == 256) STM_OCC(double, 3, 256); else if (block == 512) STM_OCC(double, 3, 512); else STM_OCC(double, 3, 1024); }
+  if (dim == 3 && inner_fp32) { if (block == 256) STM_OCC(float, 3, 256); else if (block == 512) STM_OCC(float, 3, 512); else STM_OCC(float, 3, 1024); }
+#undef STM_OCC
+  if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds_bytes) != hipSuccess) return 0;
+  return nb;
 }
 
 }  // namespace stm

@@ -47,6 +47,8 @@ struct stm_ctx {
   size_t int_cap = 0;
   double* d_scratch = nullptr;
   size_t scratch_cap = 0;
+  unsigned char* d_sync = nullptr;
+  size_t sync_cap = 0;
   // phase timing
   hipEvent_t ev[2] = {nullptr, nullptr};
   stm_timings tm{};
@@ -153,7 +155,7 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
 
 void fill_defaults(stm_problem& p) {
   const bool mixed = p.precision == STM_PREC_MIXED;
-  if (p.newton_tol <= 0) p.newton_tol = mixed ? 1e-10 : 1e-12;
+  if (p.newton_tol <= 0) p.newton_tol = 1e-10;
   if (p.newton_max <= 0) p.newton_max = 30;
   if (p.gmres_rtol <= 0) p.gmres_rtol = mixed ? 1e-5 : 1e-10;
   if (p.gmres_restart <= 0) p.gmres_restart = 16;
@@ -161,7 +163,7 @@ void fill_defaults(stm_problem& p) {
   if (p.smooth_omega <= 0) p.smooth_omega = 0.7;
   if (p.coarse_sweeps <= 0) p.coarse_sweeps = 8;
   if (p.cheb_ratio <= 1) p.cheb_ratio = p.dim == 2 ? 10.0 : 30.0;
-  if (p.lds_kb <= 0) p.lds_kb = 64;
+  if (p.lds_kb <= 0) p.lds_kb = 144;
   if (p.mg_levels == 0) p.mg_levels = 1;
   if (p.max_lanes <= 0) p.max_lanes = 1024;
 }
@@ -228,7 +230,7 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   d.off_tact = take(8 * (size_t)n0);
   d.off_V = take(ti * vs * (R + 1));
   d.off_Z = take(ti * vs * R);
-  d.off_rhs = 0;
+  d.off_kd = take(ti * n0);
   for (int k = 0; k < nmg; ++k) {
     const GridDev& g = d.g[k];
     d.off_mgT[k] = take(ti * g.n);
@@ -252,7 +254,9 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
       for (int ry = 1; ry <= g0.ny; ++ry) {
         const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
         const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
-        const size_t bytes = 2 * fb * (size_t)sy * sz * g0.nx + 16 + 8 * (size_t)ey * ez * g0.ex;
+        const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
+        // four staged nodal fields, element conductivities, element contributions
+        const size_t bytes = 4 * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex;
         if (bytes > budget) break;
         const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
         if (eff > best) {
@@ -289,23 +293,107 @@ stm_status timed_end(stm_ctx* c, double* acc_ms) {
   return STM_OK;
 }
 
-// Launch the team solver over a list of tasks (synchronous).
-stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& tasks, int block) {
-  if (tasks.empty()) return STM_OK;
-  stm_status st = grow(c, &c->d_tasks, &c->tasks_cap, tasks.size() * sizeof(TeamTask));
+// Expand teams into one TeamTask per workgroup and launch the solver
+// (synchronous).  Members of a team with G > 1 are placed on workgroup
+// indices of one residue class mod 8, so that with round-robin dispatch over
+// the 8 XCDs a team shares one L2; correctness does not depend on it.
+stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
+  if (teams.empty()) return STM_OK;
+  int n_blocks = 0, n_multi = 0, max_g = 1;
+  for (auto& t : teams) {
+    n_blocks += t.G;
+    if (t.G > 1) ++n_multi;
+    max_g = std::max(max_g, t.G);
+  }
+  const bool coop = max_g > 1;
+  // barrier counters (one 128-byte line per team) + partials + fault flag
+  const size_t ctr_words = (size_t)teams.size() * 32;
+  const size_t part_doubles = (size_t)teams.size() * 2 * max_g * 16;
+  const size_t sync_bytes = ctr_words * 4 + part_doubles * 8 + 256;
+  stm_status st = grow(c, &c->d_sync, &c->sync_cap, sync_bytes);
   if (st != STM_OK) return st;
-  STM_HIP(c, hipMemcpyAsync(c->d_tasks, tasks.data(), tasks.size() * sizeof(TeamTask), hipMemcpyHostToDevice,
+  unsigned* ctr = reinterpret_cast<unsigned*>(c->d_sync);
+  double* part = reinterpret_cast<double*>(c->d_sync + ctr_words * 4);
+  int* fault = reinterpret_cast<int*>(c->d_sync + ctr_words * 4 + part_doubles * 8);
+  // placement: free slots per residue class
+  std::vector<std::vector<int>> cls(8);
+  for (int b = n_blocks - 1; b >= 0; --b) cls[b % 8].push_back(b);
+  std::vector<TeamTask> blocks(n_blocks);
+  std::vector<char> used(n_blocks, 0);
+  auto take_any = [&]() {
+    for (int r = 0; r < 8; ++r)
+      while (!cls[r].empty()) {
+        const int b = cls[r].back();
+        cls[r].pop_back();
+        if (!used[b]) return b;
+      }
+    return -1;
+  };
+  int next_cls = 0;
+  for (size_t t = 0; t < teams.size(); ++t) {
+    TeamTask base = teams[t];
+    base.bar = ctr + t * 32;
+    base.part = part + t * 2 * max_g * 16;
+    base.fault = fault;
+    if (base.G == 1) continue;
+    int r = next_cls;
+    next_cls = (next_cls + 1) % 8;
+    for (int g = 0; g < base.G; ++g) {
+      int b = -1;
+      while (!cls[r].empty() && b < 0) {
+        const int cand = cls[r].back();
+        cls[r].pop_back();
+        if (!used[cand]) b = cand;
+      }
+      if (b < 0) b = take_any();
+      used[b] = 1;
+      blocks[b] = base;
+      blocks[b].rank = g;
+    }
+  }
+  for (size_t t = 0; t < teams.size(); ++t) {
+    if (teams[t].G != 1) continue;
+    const int b = take_any();
+    used[b] = 1;
+    blocks[b] = teams[t];
+    blocks[b].rank = 0;
+    blocks[b].bar = ctr + t * 32;
+    blocks[b].part = part + t * 2 * 16;
+    blocks[b].fault = fault;
+  }
+  (void)n_multi;
+  if ((st = grow(c, &c->d_tasks, &c->tasks_cap, blocks.size() * sizeof(TeamTask)))) return st;
+  STM_HIP(c, hipMemcpyAsync(c->d_tasks, blocks.data(), blocks.size() * sizeof(TeamTask), hipMemcpyHostToDevice,
                             c->stream));
+  hipError_t e = launch_fill_u32(ctr, 0u, (int64_t)(sync_bytes / 4), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "fill");
   if ((st = timed_begin(c))) return st;
-  hipError_t e = launch_team_solver(c->p.dim, c->inner_fp32, c->d_levels, c->d_tasks, (int)tasks.size(), c->prm,
-                                    block, (size_t)c->stage_bytes, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "team solver launch");
+  e = launch_team_solver(c->p.dim, c->inner_fp32, c->d_levels, c->d_tasks, n_blocks, c->prm, block,
+                         (size_t)c->stage_bytes, coop, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, coop ? "cooperative team solver launch" : "team solver launch");
   // the task table stays alive until the kernel has finished
   if ((st = timed_end(c, &c->tm.solve_ms))) return st;
+  int hf = 0;
+  STM_HIP(c, hipMemcpy(&hf, fault, sizeof(int), hipMemcpyDeviceToHost));
+  if (hf) return fail(c, STM_E_DEVICE, "a team barrier wait timed out");
   c->tm.solve_launches += 1;
-  c->tm.solve_teams = (int)tasks.size();
+  c->tm.solve_teams = (int)teams.size();
   c->tm.solve_block = block;
+  c->tm.solve_blocks = n_blocks;
   return STM_OK;
+}
+
+// Largest team size a level allows: single-grid V-cycle and >= 8 node rows per member.
+int max_team(const stm_ctx* c, int level) {
+  const LevelDev& d = c->levels[level].dev;
+  if (d.nmg > 1) return 1;
+  return std::max(1, std::min(16, d.g[0].ny / 8));
+}
+
+// Workgroups that can be resident at once for the solver configuration.
+int block_capacity(stm_ctx* c, int block) {
+  const int occ = team_solver_occupancy(c->p.dim, c->inner_fp32, block, (size_t)c->stage_bytes);
+  return std::max(1, occ) * c->n_cu;
 }
 
 void reset_timings(stm_ctx* c) { c->tm = stm_timings{}; }
@@ -396,6 +484,7 @@ void stm_destroy(stm_ctx* c) {
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->d_int) (void)hipFree(c->d_int);
   if (c->d_scratch) (void)hipFree(c->d_scratch);
+  if (c->d_sync) (void)hipFree(c->d_sync);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -446,12 +535,19 @@ stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double
   stm_status st;
   if ((st = check_ptr(c, sigma, "sigma")) || (st = check_ptr(c, u, "u"))) return st;
   LevelHost& L = c->levels[level];
-  const int lanes = std::min(S, c->p.max_lanes);
+  const int block = auto_block(c->p, L.dev.g[0].n);
+  const int cap = std::min(c->p.max_lanes, block_capacity(c, block));
+  // few samples: several workgroups per sample (up to the level's limit)
+  int G = 1;
+  if (c->p.team_size > 0) G = std::min(c->p.team_size, max_team(c, level));
+  else if (S * 2 <= cap) G = std::min(max_team(c, level), std::max(1, cap / S));
+  const int lanes = std::max(1, std::min(S, cap / G));
   if ((st = grow(c, &c->work, &c->work_bytes, (size_t)lanes * L.team_bytes))) return st;
   if ((st = grow(c, &c->d_stats, &c->stats_cap, (size_t)S * sizeof(SampleStatsDev)))) return st;
   std::vector<TeamTask> tasks(lanes);
   for (int i = 0; i < lanes; ++i) {
     TeamTask& t = tasks[i];
+    t = TeamTask{};
     t.level = level;
     t.first = i;
     t.stride = lanes;
@@ -462,9 +558,10 @@ stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double
     t.t_act = nullptr;
     t.work = static_cast<unsigned char*>(c->work) + (size_t)i * L.team_bytes;
     t.stats = c->d_stats;
+    t.G = G;
   }
   reset_timings(c);
-  if ((st = run_tasks(c, tasks, auto_block(c->p, L.dev.g[0].n)))) return st;
+  if ((st = run_tasks(c, tasks, block))) return st;
   std::vector<SampleStatsDev> sd(S);
   STM_HIP(c, hipMemcpy(sd.data(), c->d_stats, S * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
   int worst = 0;
@@ -480,6 +577,7 @@ stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double
       o.final_step = sd[s].final_step;
       o.device_seconds = sd[s].ticks * 1e-8;
       o.algorithmic_bytes = sd[s].alg_bytes;
+      for (int q = 0; q < 8; ++q) o.phase_seconds[q] = sd[s].phase_ticks[q] * 1e-8;
     }
   }
   if (worst == STM_E_NONFINITE) return fail(c, STM_E_NONFINITE, "non-finite residual in a sample");
@@ -527,31 +625,51 @@ struct Group {          // all fine or all coarse members of one MLMC level
   int mlmc_level;
   bool coarse;
   int n0, n1;           // samples [n0, n1) solved in this round
-  double cost;          // estimated cost per sample (nodes x steps)
-  int lanes;
+  double cost;          // estimated workgroup-seconds per sample
+  int lanes;            // teams
+  int G;                // workgroups per team
+  int gmax;             // largest team the grid allows
 };
 
-// Lane allocation for one persistent launch: pick the smallest makespan
-// target T such that giving each group ceil(N_g / floor(T / c_g)) lanes fits
-// the lane budget (every lane of a group then solves at most floor(T / c_g)
-// samples in sequence, each warm-started from the previous one).
+// Team allocation for one persistent launch.  Pick the smallest makespan
+// target T such that the workgroups fit the budget, where a group whose
+// sample costs at most T runs one workgroup per team and floor(T / c)
+// samples in sequence per team (each warm-started from the previous), and a
+// group whose sample costs more gets teams of ceil(c / T) workgroups (at most
+// gmax) so that a sample still finishes near T.
 void allocate_lanes(std::vector<Group>& gs, int budget) {
-  double total = 0.0, biggest = 0.0;
+  double total = 0.0, floor_t = 0.0;
   for (auto& g : gs) {
     total += (g.n1 - g.n0) * g.cost;
-    biggest = std::max(biggest, g.cost);
+    floor_t = std::max(floor_t, g.cost / g.gmax);
   }
-  double T = std::max(biggest, total / std::max(budget, 1));
-  for (int iter = 0; iter < 200; ++iter) {
+  double T = std::max(floor_t, total / std::max(budget, 1));
+  for (int iter = 0; iter < 400; ++iter) {
     int used = 0;
     for (auto& g : gs) {
       const int N = g.n1 - g.n0;
-      const int per = std::max(1, (int)std::floor(T / g.cost + 1e-9));
-      g.lanes = N > 0 ? (N + per - 1) / per : 0;
-      used += g.lanes;
+      if (N <= 0) {
+        g.lanes = 0;
+        g.G = 1;
+        continue;
+      }
+      if (g.cost <= T) {
+        g.G = 1;
+        const int per = std::max(1, (int)std::floor(T / g.cost + 1e-9));
+        g.lanes = (N + per - 1) / per;
+      } else {
+        g.G = std::min(g.gmax, (int)std::ceil(g.cost / T - 1e-9));
+        const int per = std::max(1, (int)std::floor(T * g.G / g.cost + 1e-9));
+        g.lanes = (N + per - 1) / per;
+      }
+      used += g.lanes * g.G;
     }
     if (used <= budget) return;
     T *= 1.05;
+  }
+  for (auto& g : gs) {  // budget too small for any balance: one workgroup per group
+    g.G = 1;
+    g.lanes = (g.n1 > g.n0) ? 1 : 0;
   }
 }
 
@@ -660,8 +778,10 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         const LevelDev& d = c->levels[g.grid].dev;
         // model: nodes x steps plus a per-slab overhead (small grids are
         // dominated by the per-pass synchronisation); measured costs win
-        g.cost = (double)(d.g[0].n + 3000) * d.m;
+        g.cost = 2e-8 * (double)(d.g[0].n + 3000) * d.m;
         g.lanes = 0;
+        g.G = 1;
+        g.gmax = max_team(c, g.grid);
         gs.push_back(g);
       }
     }
@@ -669,20 +789,21 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
     for (auto& g : gs) all_measured = all_measured && c->measured_cost[g.grid] > 0;
     if (all_measured)
       for (auto& g : gs) g.cost = c->measured_cost[g.grid];
-    allocate_lanes(gs, lane_budget);
+    int block = 256;
+    for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
+    allocate_lanes(gs, std::min(lane_budget, block_capacity(c, block)));
     size_t ws = 0;
     for (auto& g : gs) ws += (size_t)g.lanes * (c->levels[g.grid].team_bytes + c->levels[g.grid].u_bytes);
     if ((st = grow(c, &c->work, &c->work_bytes, ws))) return st;
     std::vector<TeamTask> tasks;
     size_t woff = 0;
-    int block = 256;
-    for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
     for (auto& g : gs) {
       const LevelHost& LH = c->levels[g.grid];
       const int l = g.mlmc_level;
       const int N = g.n1 - g.n0;
       for (int i = 0; i < g.lanes; ++i) {
-        TeamTask t;
+        TeamTask t{};
+        t.G = g.G;
         t.level = g.grid;
         t.first = g.n0 + i;
         t.stride = g.lanes;
@@ -698,6 +819,21 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       }
     }
     if ((st = run_tasks(c, tasks, block))) return st;
+    // measured workgroup-seconds per sample of each grid (cost model of later calls)
+    {
+      std::vector<SampleStatsDev> tmp(nst);
+      STM_HIP(c, hipMemcpy(tmp.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
+      std::vector<double> acc(L1, 0.0), cnt(L1, 0.0);
+      for (auto& g : gs) {
+        const size_t base = g.coarse ? off_stc[g.mlmc_level] : off_stf[g.mlmc_level];
+        for (int i = g.n0; i < g.n1; ++i) {
+          acc[g.grid] += tmp[base + i].ticks * 1e-8 * g.G;
+          cnt[g.grid] += 1.0;
+        }
+      }
+      for (int l = 0; l < L1; ++l)
+        if (cnt[l] > 0) c->measured_cost[l] = acc[l] / cnt[l];
+    }
     for (int l = 0; l < L1; ++l) Ndone[l] = std::max(Ndone[l], Ntarget[l]);
     // 3) statistics over all samples so far
     if (out->level_mean == nullptr || out->level_var == nullptr) {
@@ -748,16 +884,8 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       }
     }
     STM_HIP(c, hipMemcpy(sh.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
-    for (int l = 0; l < L1; ++l) {
-      double t = 0.0, tf = 0.0;
-      for (int i = 0; i < Ndone[l]; ++i) {
-        tf += sh[off_stf[l] + i].ticks * 1e-8;
-        if (l > 0) t += sh[off_stc[l] + i].ticks * 1e-8;
-      }
-      t += tf;
-      cost[l] = t / std::max(1, Ndone[l]);
-      if (Ndone[l] > 0) c->measured_cost[l] = tf / Ndone[l];
-    }
+    for (int l = 0; l < L1; ++l)  // workgroup-seconds per sample pair of the level
+      cost[l] = c->measured_cost[l] + (l > 0 ? c->measured_cost[l - 1] : 0.0);
     if (!adaptive) break;
     // 4) Giles allocation: N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k))
     double ssum = 0.0;

@@ -33,7 +33,7 @@ struct LevelDev {
   // team workspace layout (bytes from the team base)
   int64_t off_u, off_uprev, off_wk1, off_tact;          // float64 [n0]
   int64_t off_V, off_Z;                                 // inner [restart+1][n0], [restart][n0]
-  int64_t off_rhs;                                      // inner [n0] (restart right-hand side)
+  int64_t off_kd;                                       // inner [n0] stiffness diagonal of grid 0
   int64_t off_mgX[kMaxMG], off_mgT[kMaxMG], off_mgB[kMaxMG], off_mgW[kMaxMG];  // inner [n_l]
   int64_t off_mgD[kMaxMG];                              // inner [ne_l][4] element tensors (l >= 1)
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
@@ -62,7 +62,10 @@ struct SolverParams {
 
 constexpr int kMaxSweeps = 32;
 
-// A team (one workgroup) solves `count` samples s = first + i * stride in order.
+// A team of G workgroups solves `count` samples s = first + i * stride in
+// order.  One TeamTask per workgroup: the members of a team carry identical
+// fields except `rank`.  With G > 1 each member owns a band of node rows of
+// the level's grid and the members meet at team barriers.
 struct TeamTask {
   int level;                 // index into the LevelDev table of the launch
   int first, stride, count;
@@ -72,6 +75,10 @@ struct TeamTask {
   double* t_act;             // [*][n0] or null
   unsigned char* work;       // team workspace
   struct SampleStatsDev* stats;  // [*] or null
+  int rank, G;               // member rank, team size
+  unsigned* bar;             // team barrier counter, zero at launch (G > 1)
+  double* part;              // team reduction partials [2][G][16] (G > 1)
+  int* fault;                // set to 1 when a team barrier wait times out
 };
 
 struct SampleStatsDev {
@@ -84,6 +91,7 @@ struct SampleStatsDev {
   int censored;
   int pad;
   double alg_bytes;          // bytes the sample's passes must move (per-pass model)
+  long long phase_ticks[8];  // per-phase wall-clock ticks when built with STM_PHASE_TIMERS, else 0
 };
 
 // ---------------------------------------------------------------------------

@@ -122,6 +122,41 @@ def test_warm_start_and_explicit_guess_reach_same_solution(torch_dev):
     assert _rel(c.cpu().numpy(), a.cpu().numpy()) < 1e-10
 
 
+@pytest.mark.parametrize("dim,G", [(2, 2), (2, 4), (3, 2)])
+def test_multi_workgroup_teams_match_oracle(torch_dev, dim, G):
+    """Samples split over G workgroups (row bands, team barriers, rank-ordered
+    reductions) reach the oracle solution."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    if dim == 2:
+        wl = _wl(levels=[(33, 33)], steps=[24])
+    else:
+        wl = stinputs.workload("slab3d", levels=[(17, 17, 5)], steps=[6], n_modes=8, kl_grid=(9, 9, 3),
+                               precision="fp64", ic_radius=0.3, sigma_f0=4e-3)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl, team_size=G)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    assert ctx.timings()["solve_blocks"] == G * ctx.timings()["solve_teams"]
+    U_ref, _ = oapi.st_solve(wl, 0, sig)
+    assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+
+
+def test_nonconvergence_is_reported_not_hidden(torch_dev):
+    """One backward-Euler step over the whole horizon (dt = T) makes the slab
+    operator indefinite; the solver stops at its Newton limit and says so."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context, StmError
+    wl = _wl(levels=[(17, 17)], steps=[1])
+    modes, xi = _inputs(wl, 1)
+    sig = torch.from_numpy(oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])).to(dev)
+    ctx = Context(wl, newton_max=5)
+    with pytest.raises(StmError) as e:
+        ctx.st_solve(0, sig)
+    assert e.value.code == "STM_E_NOT_CONVERGED"
+
+
 def test_activation_map_kernel_vs_oracle_on_synthetic_series(torch_dev):
     torch, dev = torch_dev
     from paper_1911_06066_amd import Context
