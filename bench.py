@@ -21,6 +21,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL = "st_team_kernel"
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources the solver kernel is built from."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1911_06066_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload):
+    """HBM bytes per launch of the solver kernel from the committed counter summary.
+
+    The summary holds FETCH_SIZE + WRITE_SIZE of the solver launch scaled by the
+    same counters on a copy of known size.  Returns None when no summary exists
+    for the workload or the kernel sources changed since it was taken.
+    """
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (KERNEL, workload))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("#", "|", "*", " ")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def _oracle_worker(args):
@@ -128,6 +162,8 @@ def main():
     value = samples / (ms / 1e3)
     dof_steps = float(out["dof_steps"])
     achieved = float(np.mean(solve_bytes)) / (float(np.mean(solve_ms)) * 1e-3) / 1e9
+    default_cfg = not (args.precision or args.max_lanes or args.block)
+    traffic = profiled_traffic(wl["name"]) if default_cfg else None
 
     line = {
         "metric": "MLMC samples/sec & DOF*steps/s at fixed RMSE; stencil HBM GB/s vs peak",
@@ -158,8 +194,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "st_team_kernel",
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": KERNEL,
             "kernel_ms": float(np.mean(solve_ms)),
         },
         "detail": {
