@@ -43,9 +43,12 @@ namespace stm {
 #define STM_T0(v) long long v = wall_clock64()
 #define STM_T1(v, slot) \
   if (threadIdx.x == 0) ph_acc[slot] += wall_clock64() - v
+#define STM_T1P(v, slot) \
+  if (threadIdx.x == 0) ph[slot] += wall_clock64() - v
 #else
 #define STM_T0(v)
 #define STM_T1(v, slot)
+#define STM_T1P(v, slot)
 #endif
 
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
@@ -53,14 +56,14 @@ constexpr unsigned kSpinLimit = 1u << 25;
 
 template <int DIM>
 __device__ __forceinline__ void decode(const GridDev& g, int idx, int& i, int& j, int& k) {
-  i = idx % g.nx;
-  const int r = idx / g.nx;
+  const int r = fdiv(idx, g.mnx);
+  i = idx - r * g.nx;
   if constexpr (DIM == 2) {
     j = r;
     k = 0;
   } else {
-    j = r % g.ny;
-    k = r / g.ny;
+    k = fdiv(r, g.mny);
+    j = r - k * g.ny;
   }
 }
 
@@ -122,7 +125,8 @@ struct Team {
   int64_t vstride;
   unsigned char* work;
   unsigned char* smem;   // dynamic LDS staging area
-  TI* kdiag0;            // diagonal of the stiffness matrix on grid 0 (per sample)
+  double* kdiag0;        // diagonal of the stiffness matrix on grid 0 (per sample)
+  TI* dinv;              // inverse diagonal of the slab operator on grid 0 (per Newton step)
   double* omega;         // shared: per grid, the sweep weights [kMaxMG][kMaxSweeps]
   double* red;           // shared: block reduction scratch
   // team membership
@@ -138,6 +142,9 @@ struct Team {
   // writes counted once per pass (neighbour and halo re-reads are cache/LDS
   // traffic, not counted).  Uniform across the team; rank 0 reports it.
   mutable double bytes;
+#ifdef STM_PHASE_TIMERS
+  long long* ph;         // shared per-phase tick accumulators
+#endif
 
   __device__ __forceinline__ double dbytes(int l) const {
     return l == 0 ? 8.0 * L->g[0].ne : 4.0 * sizeof(TI) * L->g[l].ne;
@@ -224,6 +231,7 @@ struct Team {
     if constexpr (DIM == 2) {
       return jb0 * g.nx + q;
     } else {
+      if (G == 1) return q;
       const int w = (jb1 - jb0) * g.nx;
       const int kk = q / w;
       return (kk * g.ny + jb0) * g.nx + (q - kk * w);
@@ -232,20 +240,23 @@ struct Team {
 
   // ---- staged pass on grid 0 ----------------------------------------------
   // For each tile of the owned rows: stage nodal fields f0, f1 (with a
-  // one-node halo), f2, f3 (optional, may be null) and the tile's element
-  // conductivities into LDS, every thread issuing all of its loads before
-  // using any; compute every element's vertex contributions of
+  // one-node halo), f2, f3 (optional, may be null), the tile's element
+  // conductivities and fibre rows into LDS, every thread issuing all of its
+  // loads before using any; compute every element's vertex contributions of
   // M mval + K kval once (phase A, kval/mval from the raw f0, f1 values); sum
   // the adjacent elements' contributions per node (phase B) and call
   // body(idx, i, j, k, y, o0, o1, o2, o3) with o* the staged values at the
-  // node.  Phases A and B read LDS only.  Ends with a team barrier.
+  // node.  Phases A and B read LDS only; every LDS array is laid out so that
+  // consecutive lanes touch consecutive words.  Index decoding uses exact
+  // multiply-high division.  Ends with a team barrier.
   template <typename T, typename KV, typename MV, typename Body>
   __device__ void staged(const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
                          const T* __restrict__ f3, KV kval, MV mval, Body body) const {
     constexpr int NV = (DIM == 3) ? 8 : 4;
     constexpr int U = 4;
     const GridDev& g = L->g[0];
-    const int nx = g.nx;
+    const int nx = g.nx, EX = g.ex;
+    const unsigned mnx = g.mnx, mex = g.mex;
     const int Ry = sizeof(T) == 8 ? L->tile_y8 : L->tile_y4;
     const int Rz = (DIM == 3) ? (sizeof(T) == 8 ? L->tile_z8 : L->tile_z4) : 1;
     const int nzz = (DIM == 3) ? g.nz : 1;
@@ -261,30 +272,46 @@ struct Team {
     for (int k0 = 0; k0 < nzz; k0 += Rz) {
       for (int j0 = jb0; j0 < jb1; j0 += Ry) {
         const int je = min(j0 + Ry, jb1);  // computed rows [j0, je)
+        const int ke = min(k0 + Rz, nzz);  // computed planes [k0, ke)
         const int jr0 = max(j0 - 1, 0), jr1 = min(je, g.ny - 1);
-        const int kr0 = (DIM == 3) ? max(k0 - 1, 0) : 0, kr1 = (DIM == 3) ? min(k0 + Rz, g.nz - 1) : 0;
+        const int kr0 = (DIM == 3) ? max(k0 - 1, 0) : 0, kr1 = (DIM == 3) ? min(ke, g.nz - 1) : 0;
         const int sy = jr1 - jr0 + 1;
-        const int nst = sy * (kr1 - kr0 + 1) * nx;
+        const int lay = sy * nx;  // staged nodes per plane
+        const int nst = lay * (kr1 - kr0 + 1);
         const int ey0 = max(j0 - 1, 0), ey1 = min(je - 1, g.ey - 1);
-        const int ez0 = (DIM == 3) ? max(k0 - 1, 0) : 0, ez1 = (DIM == 3) ? min(k0 + Rz - 1, g.ez - 1) : 0;
+        const int ez0 = (DIM == 3) ? max(k0 - 1, 0) : 0, ez1 = (DIM == 3) ? min(ke - 1, g.ez - 1) : 0;
         const int sey = ey1 - ey0 + 1;
-        const int nse = sey * (ez1 - ez0 + 1) * g.ex;
+        const int elay = sey * EX;  // staged elements per plane
+        const int nse = elay * (ez1 - ez0 + 1);
+        const int nfr = (DIM == 3) ? (ez1 - ez0 + 1) : sey;  // fibre rows
+        const int fr0 = (DIM == 3) ? ez0 : ey0;
+        const unsigned mlay = (DIM == 3) ? fdiv_magic((unsigned)lay) : 0u;
+        const unsigned melay = (DIM == 3) ? fdiv_magic((unsigned)elay) : 0u;
         T* l0 = reinterpret_cast<T*>(smem);
         T* l1 = l0 + nst;
         T* l2 = l1 + nst;
         T* l3 = l2 + (f2 ? nst : 0);
         double* ls = reinterpret_cast<double*>(smem + ((nf * (size_t)nst * sizeof(T) + 15) & ~(size_t)15));
-        T* lc = reinterpret_cast<T*>(ls + nse);
+        T* lc = reinterpret_cast<T*>(ls + nse);  // [NV][nse]
+        double* lf = reinterpret_cast<double*>(
+            reinterpret_cast<unsigned char*>(lc) + ((NV * (size_t)nse * sizeof(T) + 15) & ~(size_t)15));
         // ---- stage: batched loads, then LDS stores ----
+        STM_T0(t_st);
+        const int gq0 = (DIM == 3) ? (kr0 * g.ny + jr0) * nx : jr0 * nx;
+        const int plane = g.ny * nx;
         for (int qb = threadIdx.x; qb < nst; qb += BLOCK * U) {
           T r0[U], r1[U], r2[U], r3[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int q = qb + u * BLOCK;
             if (q < nst) {
-              const int i = q % nx, r = q / nx;
-              const int jj = jr0 + r % sy, kk = kr0 + r / sy;
-              const int gq = (DIM == 3) ? ((kk * g.ny + jj) * nx + i) : (jj * nx + i);
+              int gq;
+              if constexpr (DIM == 3) {
+                const int lz = fdiv(q, mlay);
+                gq = gq0 + lz * plane + (q - lz * lay);
+              } else {
+                gq = gq0 + q;
+              }
               r0[u] = f0[gq];
               r1[u] = f1[gq];
               if (f2) r2[u] = f2[gq];
@@ -302,34 +329,52 @@ struct Team {
             }
           }
         }
-        for (int qb = threadIdx.x; qb < nse; qb += BLOCK * U) {
-          double rs[U];
+        {
+          const int ge0 = (DIM == 3) ? (ez0 * g.ey + ey0) * EX : ey0 * EX;
+          const int eplane = g.ey * EX;
+          for (int qb = threadIdx.x; qb < nse; qb += BLOCK * U) {
+            double rs[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int q = qb + u * BLOCK;
-            if (q < nse) {
-              const int ex = q % g.ex, r = q / g.ex;
-              const int ey = ey0 + r % sey, ez = ez0 + r / sey;
-              rs[u] = sg[(DIM == 3) ? ((ez * g.ey + ey) * g.ex + ex) : (ey * g.ex + ex)];
+            for (int u = 0; u < U; ++u) {
+              const int q = qb + u * BLOCK;
+              if (q < nse) {
+                int ge;
+                if constexpr (DIM == 3) {
+                  const int lz = fdiv(q, melay);
+                  ge = ge0 + lz * eplane + (q - lz * elay);
+                } else {
+                  ge = ge0 + q;
+                }
+                rs[u] = sg[ge];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int q = qb + u * BLOCK;
+              if (q < nse) ls[q] = rs[u];
             }
           }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int q = qb + u * BLOCK;
-            if (q < nse) ls[q] = rs[u];
-          }
+          for (int q = threadIdx.x; q < 3 * nfr; q += BLOCK) lf[q] = fib[3 * fr0 + q];
         }
         __syncthreads();
+        STM_T1P(t_st, 6);
+        STM_T0(t_pa);
         // ---- phase A: element contributions ----
         for (int q = threadIdx.x; q < nse; q += BLOCK) {
-          const int ex = q % g.ex, r = q / g.ex;
-          const int ey = ey0 + r % sey, ez = ez0 + r / sey;
-          const auto D = tensor_from<T, DIM>(ls[q], fib + 3 * ((DIM == 3) ? ez : ey), tau);
+          int lz = 0, rem = q;
+          if constexpr (DIM == 3) {
+            lz = fdiv(q, melay);
+            rem = q - lz * elay;
+          }
+          const int r = fdiv(rem, mex);
+          const int ex = rem - r * EX;
+          const int ey = ey0 + r, ez = ez0 + lz;
+          const auto D = tensor_from<T, DIM>(ls[q], lf + 3 * ((DIM == 3) ? lz : r), tau);
           const int base = ((ez - kr0) * sy + (ey - jr0)) * nx + ex;
           T kv[NV], mv[NV], out[NV];
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const int o = base + ((v >> 2) & 1) * sy * nx + ((v >> 1) & 1) * nx + (v & 1);
+            const int o = base + ((v >> 2) & 1) * lay + ((v >> 1) & 1) * nx + (v & 1);
             const T a = l0[o], b = l1[o];
             kv[v] = kval(a, b);
             mv[v] = mval(a, b);
@@ -337,32 +382,42 @@ struct Team {
           if constexpr (DIM == 3) elem_apply_3d<T>(kv, mv, D, cxx, cyy, czz, cxy, cm, out);
           else elem_apply_2d<T>(kv, mv, D, cxx, cyy, cm, out);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) lc[q * NV + v] = out[v];
+          for (int v = 0; v < NV; ++v) lc[v * nse + q] = out[v];
         }
         __syncthreads();
+        STM_T1P(t_pa, 7);
         // ---- phase B: nodes of the tile ----
-        const int cy = je - j0, cz = min(k0 + Rz, nzz) - k0;
-        const int nc = cy * cz * nx;
+        const int cy = je - j0;
+        const int clay = cy * nx;
+        const int nc = clay * (ke - k0);
+        const unsigned mclay = (DIM == 3) ? fdiv_magic((unsigned)clay) : 0u;
         for (int q = threadIdx.x; q < nc; q += BLOCK) {
-          const int i = q % nx, r = q / nx;
-          const int j = j0 + r % cy, k = k0 + r / cy;
+          int lz = 0, rem = q;
+          if constexpr (DIM == 3) {
+            lz = fdiv(q, mclay);
+            rem = q - lz * clay;
+          }
+          const int r = fdiv(rem, mnx);
+          const int i = rem - r * nx;
+          const int j = j0 + r, k = k0 + lz;
           const int idx = (DIM == 3) ? ((k * g.ny + j) * nx + i) : (j * nx + i);
           T y = T(0);
 #pragma unroll
           for (int c = 0; c < ((DIM == 3) ? 2 : 1); ++c) {
             const int ez = k - 1 + c;
-            if (DIM == 3 && (ez < 0 || ez >= g.ez)) continue;
+            const bool okz = (DIM == 2) || (ez >= 0 && ez < g.ez);
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
               const int ey = j - 1 + b;
-              if (ey < 0 || ey >= g.ey) continue;
+              const bool oky = okz && ey >= 0 && ey < g.ey;
 #pragma unroll
               for (int a = 0; a < 2; ++a) {
                 const int ex = i - 1 + a;
-                if (ex < 0 || ex >= g.ex) continue;
-                const int el = (((DIM == 3) ? (ez - ez0) : 0) * sey + (ey - ey0)) * g.ex + ex;
+                const bool ok = oky && ex >= 0 && ex < EX;
+                const int el = (((DIM == 3) ? (ez - ez0) : 0) * sey + (ey - ey0)) * EX + ex;
                 const int v = (1 - a) + 2 * (1 - b) + ((DIM == 3) ? 4 * (1 - c) : 0);
-                y += lc[el * NV + v];
+                const T cv = lc[v * nse + (ok ? el : 0)];
+                y += ok ? cv : T(0);
               }
             }
           }
@@ -424,41 +479,32 @@ struct Team {
     bytes += (x ? 5.0 : 4.0) * sizeof(TI) * n + (x ? dbytes(l) : 0.0);
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
-      const TI cmd = cmd0();
       if (!x) {
         const int nb = nband();
+        const TI* __restrict__ di = dinv;
         for (int qb = threadIdx.x; qb < nb; qb += BLOCK * 4) {
-          TI rb[4], rk[4], rw[4];
+          TI rb[4], rd[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int q = qb + v * BLOCK;
             if (q < nb) {
               const int idx = bidx(q);
               rb[v] = b[idx];
-              rk[v] = kdiag0[idx];
-              rw[v] = w[idx];
+              rd[v] = di[idx];
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int q = qb + v * BLOCK;
-            if (q < nb) {
-              const int idx = bidx(q);
-              int i, j, k;
-              decode<DIM>(L->g[0], idx, i, j, k);
-              out[idx] = om * rb[v] / (rk[v] + TI(nel0(i, j, k)) * cmd * rw[v]);
-            }
+            if (q < nb) out[bidx(q)] = om * rb[v] * rd[v];
           }
         }
         sync();
         return;
       }
       staged<TI>(
-          x, w, b, kdiag0, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
-          [&](int idx, int i, int j, int k, TI y, TI xo, TI wo, TI bo, TI kdo) {
-            const TI d = kdo + TI(nel0(i, j, k)) * cmd * wo;
-            out[idx] = xo + om * (bo - y) / d;
-          });
+          x, w, b, dinv, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+          [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
       return;
     }
     if (!x) {
@@ -599,12 +645,10 @@ struct Team {
       double nn[2] = {0.0, 0.0};
       if (l == 0) {
         const TI* __restrict__ w = mgW(0);
-        const TI cmd = cmd0();
         staged<TI>(
-            x0, w, kdiag0, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
-            [&](int idx, int i, int j, int k, TI ax, TI xown, TI wo, TI kdo, TI) {
-              const TI d = kdo + TI(nel0(i, j, k)) * cmd * wo;
-              const TI y = ax / d;
+            x0, w, dinv, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+            [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
+              const TI y = ax * dio;
               x1[idx] = y;
               nn[0] += double(y) * double(y);
               nn[1] += double(xown) * double(xown);
@@ -662,7 +706,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   __shared__ double omega_tab[kMaxMG * kMaxSweeps];
   __shared__ double sh_resid;
 #ifdef STM_PHASE_TIMERS
-  long long ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  __shared__ long long ph_acc[8];
+  if (threadIdx.x < 8) ph_acc[threadIdx.x] = 0;
+  __syncthreads();
 #endif
 
   const TeamTask task = tasks[blockIdx.x];
@@ -685,6 +731,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   tm.gen = 0;
   tm.rslot = 0;
   tm.broken = false;
+#ifdef STM_PHASE_TIMERS
+  tm.ph = ph_acc;
+#endif
   const GridDev g0 = L->g[0];
   tm.jb0 = (int)((long long)task.rank * g0.ny / task.G);
   tm.jb1 = (int)((long long)(task.rank + 1) * g0.ny / task.G);
@@ -695,7 +744,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   double* __restrict__ wk1 = reinterpret_cast<double*>(task.work + L->off_wk1);
   double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
   tm.V = reinterpret_cast<TI*>(task.work + L->off_V);
-  tm.kdiag0 = reinterpret_cast<TI*>(task.work + L->off_kd);
+  tm.kdiag0 = reinterpret_cast<double*>(task.work + L->off_kd);
+  tm.dinv = reinterpret_cast<TI*>(task.work + L->off_dinv);
   tm.Z = reinterpret_cast<TI*>(task.work + L->off_Z);
   const int64_t vs = (int64_t)((n0 + 63) & ~63);
   tm.vstride = vs;
@@ -778,7 +828,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             return tensor_from<double, DIM>(tm.sigma[e], L->fib + 3 * ((DIM == 3) ? ez : ey), tau);
           },
           0.0, &dd);
-      tm.kdiag0[idx] = TI(dd);
+      tm.kdiag0[idx] = dd;
       const double x = i * g0.hx - L->ic_cx, y = j * g0.hy - L->ic_cy, zc = (DIM == 3) ? (k * g0.hz - L->ic_cz) : 0.0;
       const double v = (x * x + y * y + zc * zc <= L->ic_r2) ? 1.0 : 0.0;
       uprev[idx] = v;
@@ -818,17 +868,23 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         TI* w0 = tm.mgW(0);
         double rr[1] = {0.0};
         STM_T0(t_res);
-        tm.bytes += 16.0 * n0 + 8.0 * g0.ne + 2.0 * sizeof(TI) * n0;
+        tm.bytes += 24.0 * n0 + 8.0 * g0.ne + 3.0 * sizeof(TI) * n0;
         for (int l = 1; l < L->nmg; ++l) tm.bytes += (8.0 + sizeof(TI)) * L->g[l].n;
-        tm.template staged<double>(
-            u, uprev, (const double*)nullptr, (const double*)nullptr, [](double a, double) { return a; },
-            [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
-            [&](int idx, int, int, int, double y, double uown, double, double, double) {
-              const double r = -y;
-              V0[idx] = TI(r);
-              w0[idx] = TI(inv_dt - react_d(uown, kr, ar));
-              rr[0] += r * r;
-            });
+        {
+          TI* __restrict__ di = tm.dinv;
+          const double cmd = (DIM == 3) ? 8.0 * g0.hx * g0.hy * g0.hz / 216.0 : 4.0 * g0.hx * g0.hy / 36.0;
+          tm.template staged<double>(
+              u, uprev, tm.kdiag0, (const double*)nullptr, [](double a, double) { return a; },
+              [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
+              [&](int idx, int i, int j, int k, double y, double uown, double, double kd, double) {
+                const double r = -y;
+                const double w = inv_dt - react_d(uown, kr, ar);
+                V0[idx] = TI(r);
+                w0[idx] = TI(w);
+                di[idx] = TI(1.0 / (kd + tm.nel0(i, j, k) * cmd * w));
+                rr[0] += r * r;
+              });
+        }
         for (int l = 1; l < L->nmg; ++l) {  // G == 1 here
           const GridDev& gc = L->g[l];
           TI* wl = tm.mgW(l);
@@ -915,8 +971,11 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             }
           }
           tm.template tsum<9>(d);
-          if (tid == 0)
-            for (int q = 0; q < nk0; ++q) H[q * kMaxRestart + j] = sc[q] * sc[j] * d[q];
+          if (tid == 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (q < nk0) H[q * kMaxRestart + j] = sc[q] * sc[j] * d[q];
+          }
           for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
             const int nk = min(j + 1 - k0, 8);
             tm.bytes += (1.0 + nk) * sizeof(TI) * n0;
@@ -930,8 +989,11 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 if (p < nk) d[p] += double(tm.V[(k0 + p) * vs + idx]) * wd;
             }
             tm.template tsum<9>(d);
-            if (tid == 0)
-              for (int q = 0; q < nk; ++q) H[(k0 + q) * kMaxRestart + j] = sc[k0 + q] * sc[j] * d[q];
+            if (tid == 0) {
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (q < nk) H[(k0 + q) * kMaxRestart + j] = sc[k0 + q] * sc[j] * d[q];
+            }
           }
           if (tid == 0)
             for (int q = 0; q <= j; ++q) coef[q] = H[q * kMaxRestart + j] * sc[q] / sc[j];
@@ -941,25 +1003,33 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
           double nn[1] = {0.0};
           tm.bytes += (j + 3.0) * sizeof(TI) * n0;
+          // vectors in chunks of 4, all loads of a chunk issued before use
           for (int qb = tid; qb < nb; qb += BLOCK * 2) {
             double w[2];
             int ix[2];
 #pragma unroll
             for (int uu = 0; uu < 2; ++uu) {
               const int q = qb + uu * BLOCK;
-              ix[uu] = q < nb ? tm.bidx(q) : -1;
-              w[uu] = ix[uu] >= 0 ? double(Vn[ix[uu]]) : 0.0;
+              ix[uu] = q < nb ? tm.bidx(q) : 0;
+              w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
             }
-            for (int q = 0; q <= j; ++q) {
-              const TI* __restrict__ Vq = tm.V + q * vs;
-              const double cq = coef[q];
+            for (int q0 = 0; q0 <= j; q0 += 4) {
+              TI vv[4][2];
 #pragma unroll
-              for (int uu = 0; uu < 2; ++uu)
-                if (ix[uu] >= 0) w[uu] -= cq * double(Vq[ix[uu]]);
+              for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu)
+                  vv[p][uu] = (q0 + p <= j) ? tm.V[(q0 + p) * vs + ix[uu]] : TI(0);
+#pragma unroll
+              for (int p = 0; p < 4; ++p) {
+                const double cq = (q0 + p <= j) ? coef[q0 + p] : 0.0;
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[p][uu]);
+              }
             }
 #pragma unroll
             for (int uu = 0; uu < 2; ++uu) {
-              if (ix[uu] >= 0) {
+              if (qb + uu * BLOCK < nb) {
                 const TI wt = TI(w[uu]);
                 Vn[ix[uu]] = wt;
                 nn[0] += double(wt) * double(wt);
@@ -1013,19 +1083,25 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             const int q = qb + v * BLOCK;
-            ix[v] = q < nb ? tm.bidx(q) : -1;
-            uo[v] = ix[v] >= 0 ? u[ix[v]] : 0.0;
+            ix[v] = q < nb ? tm.bidx(q) : 0;
+            uo[v] = q < nb ? u[ix[v]] : 0.0;
           }
-          for (int q = 0; q < jdim; ++q) {
-            const TI* __restrict__ Zq = tm.Z + q * vs;
-            const double cq = coef[q];
+          for (int q0 = 0; q0 < jdim; q0 += 4) {
+            TI zz[4][2];
 #pragma unroll
-            for (int v = 0; v < 2; ++v)
-              if (ix[v] >= 0) dlt[v] += cq * double(Zq[ix[v]]);
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+              for (int v = 0; v < 2; ++v) zz[p][v] = (q0 + p < jdim) ? tm.Z[(q0 + p) * vs + ix[v]] : TI(0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const double cq = (q0 + p < jdim) ? coef[q0 + p] : 0.0;
+#pragma unroll
+              for (int v = 0; v < 2; ++v) dlt[v] += cq * double(zz[p][v]);
+            }
           }
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
-            if (ix[v] >= 0) {
+            if (qb + v * BLOCK < nb) {
               u[ix[v]] = uo[v] + dlt[v];
               dm = fmax(dm, fabs(dlt[v]));
             }
@@ -1105,7 +1181,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       task.stats[s] = st;
     }
 #ifdef STM_PHASE_TIMERS
-    for (int q = 0; q < 8; ++q) ph_acc[q] = 0;
+    __syncthreads();
+    if (threadIdx.x < 8) ph_acc[threadIdx.x] = 0;
 #endif
     prevU = Uout;
     have_prev = (status == 0);

@@ -108,6 +108,10 @@ GridDev make_grid(int dim, int nx, int ny, int nz, double lx, double ly, double 
   g.hx = lx / (nx - 1);
   g.hy = ly / (ny - 1);
   g.hz = dim == 3 ? lz / (nz - 1) : 1.0;
+  g.mnx = fdiv_magic(g.nx);
+  g.mny = fdiv_magic(g.ny);
+  g.mex = fdiv_magic(g.ex);
+  g.mey = fdiv_magic(g.ey);
   return g;
 }
 
@@ -144,6 +148,8 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
+    if ((int64_t)L.nx * L.ny * nz * std::max(L.nx, L.ny) >= (int64_t)1 << 32)
+      return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": grid too large for 32-bit index arithmetic");
     if (l > 0) {
       const stm_level& P = p.levels[l - 1];
       if (L.nx != 2 * P.nx - 1 || L.ny != 2 * P.ny - 1 || (p.dim == 3 && L.nz != 2 * P.nz - 1))
@@ -230,7 +236,8 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   d.off_tact = take(8 * (size_t)n0);
   d.off_V = take(ti * vs * (R + 1));
   d.off_Z = take(ti * vs * R);
-  d.off_kd = take(ti * n0);
+  d.off_kd = take(8 * (size_t)n0);
+  d.off_dinv = take(ti * n0);
   for (int k = 0; k < nmg; ++k) {
     const GridDev& g = d.g[k];
     d.off_mgT[k] = take(ti * g.n);
@@ -255,8 +262,10 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
         const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
         const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
         const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
-        // four staged nodal fields, element conductivities, element contributions
-        const size_t bytes = 4 * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex;
+        // four staged nodal fields, element conductivities, element
+        // contributions, fibre rows of the tile
+        const size_t bytes = 4 * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex + 16 +
+                             24 * (size_t)(p.dim == 2 ? ey : ez);
         if (bytes > budget) break;
         const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
         if (eff > best) {

@@ -18,7 +18,18 @@ struct GridDev {
   int ex, ey, ez;     // elements per axis
   int ne;             // elements
   double hx, hy, hz;
+  unsigned mnx, mny, mex, mey;  // division magics (fdiv_magic) of nx, ny, ex, ey
 };
+
+// Exact unsigned division by a divisor d >= 2 that is fixed for many
+// dividends: with m = ceil(2^32 / d), q / d = floor(q m / 2^32) whenever
+// q d <= 2^32 (the rounding excess of m, below d, then moves q m / 2^32 by less
+// than 1/d).  Index arithmetic keeps every dividend inside that range (the
+// host rejects grids with n * max(nx, ny) >= 2^32).
+__host__ __device__ inline unsigned fdiv_magic(unsigned d) {
+  return (unsigned)((0x100000000ull + d - 1) / d);
+}
+__device__ __forceinline__ int fdiv(int q, unsigned m) { return (int)__umulhi((unsigned)q, m); }
 
 // One MLMC level: its grid (index 0) and the coarser grids of its V-cycle.
 // Byte offsets locate every array inside a team workspace.
@@ -33,7 +44,8 @@ struct LevelDev {
   // team workspace layout (bytes from the team base)
   int64_t off_u, off_uprev, off_wk1, off_tact;          // float64 [n0]
   int64_t off_V, off_Z;                                 // inner [restart+1][n0], [restart][n0]
-  int64_t off_kd;                                       // inner [n0] stiffness diagonal of grid 0
+  int64_t off_kd;                                       // float64 [n0] stiffness diagonal of grid 0
+  int64_t off_dinv;                                     // inner [n0] inverse diagonal of the slab operator
   int64_t off_mgX[kMaxMG], off_mgT[kMaxMG], off_mgB[kMaxMG], off_mgW[kMaxMG];  // inner [n_l]
   int64_t off_mgD[kMaxMG];                              // inner [ne_l][4] element tensors (l >= 1)
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
