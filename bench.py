@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--max-lanes", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0 = skip)")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the per-level smoother tuning file")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,6 +140,10 @@ def main():
     modes = [torch.from_numpy(m).to(dev) for m in modes_h]
     xi = [torch.from_numpy(stinputs.xi(wl["name"], l, N[l], M)).to(dev) for l in range(len(N))]
     over = {}
+    from paper_1911_06066_amd import autotune
+    tuning = None if args.no_tuning else autotune.level_tuning(wl, wl["precision"])
+    if tuning:
+        over["level_tuning"] = tuning
     if args.max_lanes:
         over["max_lanes"] = args.max_lanes
     if args.block:
@@ -162,7 +167,7 @@ def main():
     value = samples / (ms / 1e3)
     dof_steps = float(out["dof_steps"])
     achieved = float(np.mean(solve_bytes)) / (float(np.mean(solve_ms)) * 1e-3) / 1e9
-    default_cfg = not (args.precision or args.max_lanes or args.block)
+    default_cfg = not (args.precision or args.max_lanes or args.block or args.no_tuning)
     traffic = profiled_traffic(wl["name"]) if default_cfg else None
 
     line = {
@@ -186,6 +191,7 @@ def main():
             "kl_modes": M,
             "precision": wl["precision"],
             "parallelism": "single GPU, one workgroup team per sample",
+            "smoother_per_level": [list(t) for t in tuning] if tuning else "defaults",
         },
         "dof_steps_per_s": dof_steps / (ms / 1e3),
         "roofline": {

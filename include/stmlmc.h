@@ -59,10 +59,16 @@ typedef enum {
 
 #define STM_MAX_LEVELS 8
 
-/* One MLMC level: nodes per axis (nz = 1 in 2D, all odd) and time steps. */
+/* One MLMC level: nodes per axis (nz = 1 in 2D, all odd) and time steps.
+ * smooth_sweeps and cheb_ratio override the problem's coarse_sweeps and
+ * cheb_ratio for this level (0 keeps the problem's value); a tuner measures
+ * them per level, since the best smoother degree depends on the slab
+ * operator's spectrum, i.e. on h and dt. */
 typedef struct {
   int nx, ny, nz;
   int m;
+  int smooth_sweeps;          /* Jacobi sweeps on the level's coarsest V-cycle grid, 0 .. 32 */
+  double cheb_ratio;          /* Chebyshev interval ratio, 0 or > 1 */
 } stm_level;
 
 /*

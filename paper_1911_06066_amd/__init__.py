@@ -57,6 +57,10 @@ def problem_from_workload(wl, **overrides):
         p.levels[i].ny = shape[1]
         p.levels[i].nz = shape[2] if dim == 3 else 1
         p.levels[i].m = m
+    for i, t in enumerate(overrides.pop("level_tuning", None) or []):
+        if t is not None:
+            p.levels[i].smooth_sweeps = int(t[0])
+            p.levels[i].cheb_ratio = float(t[1])
     p.n_modes = wl["n_modes"]
     prec = overrides.pop("precision", wl.get("precision", "fp64"))
     p.precision = _lib.PRECISIONS[prec]

@@ -1,0 +1,128 @@
+"""Per-level smoother tuner with a JSON cache.
+
+The slab operators M/dt + K - M diag f'(u) of a level have a spectrum set by
+h and dt, so the best Jacobi sweep count K and Chebyshev interval ratio differ
+between levels: more sweeps make each preconditioner application dearer but
+cut Krylov (and, through the inexact-Newton forcing, Newton) iterations.  The
+tuner solves a batch of samples of each level with every candidate (one
+workgroup per sample, as in the MLMC launch), keeps the candidate with the
+smallest mean workgroup-seconds per sample among those whose samples all
+converge, and writes the choice with its measurements to a JSON file.  The
+conductivity fields come from the level's KL modes with standard normal
+coefficients drawn from their own seed, not from the workload's samples.
+
+    python -m paper_1911_06066_amd.autotune --workload mlmc3_2d --out tuning.json
+"""
+
+import argparse
+import json
+import os
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING_DIR = os.path.join(HERE, "tuning")
+
+CANDIDATES = [(8, 10.0), (10, 10.0), (12, 10.0), (14, 10.0), (16, 10.0), (16, 20.0), (20, 10.0), (24, 10.0)]
+
+
+def tuning_path(workload, precision):
+    return os.path.join(TUNING_DIR, "%s_%s.json" % (workload, precision))
+
+
+def _level_key(wl, l):
+    return {"grid": list(wl["levels"][l]), "steps": int(wl["steps"][l])}
+
+
+def tune(wl, precision=None, samples=32, candidates=CANDIDATES, seed=4242, block=0, log=print):
+    """Measure every candidate on every level; return the tuning record."""
+    import torch
+
+    from . import Context, klmodes
+
+    precision = precision or wl.get("precision", "fp64")
+    dev = torch.device("cuda:0")
+    modes = [torch.from_numpy(m).to(dev) for m in klmodes.workload_modes(wl)]
+    gen = torch.Generator().manual_seed(seed)
+    M = wl["n_modes"]
+    rec = {"workload": wl["name"], "precision": precision, "device": torch.cuda.get_device_name(0),
+           "samples": samples, "seed": seed, "levels": []}
+    for l in range(len(wl["levels"])):
+        S = max(2, min(samples, int(wl["samples"][l]) if "samples" in wl else samples))
+        xi = torch.randn(S, M, generator=gen, dtype=torch.float64).to(dev)
+        results = []
+        for sweeps, ratio in candidates:
+            tune_l = [None] * len(wl["levels"])
+            tune_l[l] = (sweeps, ratio)
+            over = dict(precision=precision, level_tuning=tune_l, team_size=1, max_lanes=S)
+            if block:
+                over["block_threads"] = block
+            ctx = Context(wl, **over)
+            sig = ctx.kl_synthesize(l, modes[l], xi)
+            t0 = time.perf_counter()
+            try:
+                _, st = ctx.st_solve(l, sig)
+                ok = all(s["status"] == 0 for s in st)
+            except Exception as e:  # a candidate that fails to converge is skipped, not fatal
+                log("level %d sweeps %d ratio %g: %s" % (l, sweeps, ratio, e))
+                st, ok = [], False
+            wall = time.perf_counter() - t0
+            r = {"smooth_sweeps": sweeps, "cheb_ratio": ratio, "ok": ok, "wall_s": wall}
+            if st:
+                r["seconds_per_sample"] = sum(s["device_seconds"] for s in st) / len(st)
+                r["newton_per_sample"] = sum(s["newton_iters"] for s in st) / len(st)
+                r["krylov_per_sample"] = sum(s["krylov_iters"] for s in st) / len(st)
+            results.append(r)
+            log("level %d %s" % (l, json.dumps(r)))
+            ctx.close()
+        good = [r for r in results if r["ok"]]
+        best = min(good, key=lambda r: r["seconds_per_sample"]) if good else None
+        entry = dict(_level_key(wl, l))
+        entry["smooth_sweeps"] = best["smooth_sweeps"] if best else 0
+        entry["cheb_ratio"] = best["cheb_ratio"] if best else 0.0
+        entry["results"] = results
+        rec["levels"].append(entry)
+    return rec
+
+
+def level_tuning(wl, precision=None, path=None):
+    """(sweeps, ratio) per level from a tuning file, or None when there is no
+    file or it was measured for other grids."""
+    precision = precision or wl.get("precision", "fp64")
+    path = path or tuning_path(wl["name"], precision)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("precision") != precision or len(rec.get("levels", [])) != len(wl["levels"]):
+        return None
+    out = []
+    for l, e in enumerate(rec["levels"]):
+        if e["grid"] != list(wl["levels"][l]) or e["steps"] != int(wl["steps"][l]):
+            return None
+        out.append((int(e["smooth_sweeps"]), float(e["cheb_ratio"])))
+    return out
+
+
+def main():
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import stinputs
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--workload", default="mlmc3_2d")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--samples", type=int, default=32)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    wl = stinputs.workload(a.workload)
+    rec = tune(wl, a.precision, a.samples, block=a.block, log=lambda s: print(s, flush=True))
+    out = a.out or tuning_path(wl["name"], rec["precision"])
+    os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print("wrote", out, [(e["smooth_sweeps"], e["cheb_ratio"]) for e in rec["levels"]], flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,6 +51,16 @@ namespace stm {
 #define STM_T1P(v, slot)
 #endif
 
+// A wave-uniform float64 value moved to scalar registers: uniform solver state
+// (tolerances, norms, step sizes) then stays out of the vector register file,
+// which the stencil passes need.
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
 constexpr unsigned kSpinLimit = 1u << 25;
 
@@ -116,7 +126,10 @@ __device__ __forceinline__ double react_d(double u, double kr, double ar) {
   return kr * (-3.0 * u * u + 2.0 * (1.0 + ar) * u - ar);
 }
 
-template <typename TI, int DIM, int BLOCK>
+// MG: the launch contains a level with a multigrid hierarchy.  Without one the
+// V-cycle is the Chebyshev-weighted sweeps on the level's grid and no
+// coarse-grid code is compiled into the kernel (it would cost registers).
+template <typename TI, int DIM, int BLOCK, bool MG>
 struct Team {
   const LevelDev* L;
   SolverParams prm;
@@ -253,7 +266,8 @@ struct Team {
   __device__ void staged(const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
                          const T* __restrict__ f3, KV kval, MV mval, Body body) const {
     constexpr int NV = (DIM == 3) ? 8 : 4;
-    constexpr int U = 4;
+    constexpr int U = 4;                      // batched loads per thread in the staging loop
+    constexpr int UA = (DIM == 3) ? 1 : 2;    // independent elements per thread in phase A
     const GridDev& g = L->g[0];
     const int nx = g.nx, EX = g.ex;
     const unsigned mnx = g.mnx, mex = g.mex;
@@ -359,30 +373,45 @@ struct Team {
         __syncthreads();
         STM_T1P(t_st, 6);
         STM_T0(t_pa);
-        // ---- phase A: element contributions ----
-        for (int q = threadIdx.x; q < nse; q += BLOCK) {
-          int lz = 0, rem = q;
-          if constexpr (DIM == 3) {
-            lz = fdiv(q, melay);
-            rem = q - lz * elay;
-          }
-          const int r = fdiv(rem, mex);
-          const int ex = rem - r * EX;
-          const int ey = ey0 + r, ez = ez0 + lz;
-          const auto D = tensor_from<T, DIM>(ls[q], lf + 3 * ((DIM == 3) ? lz : r), tau);
-          const int base = ((ez - kr0) * sy + (ey - jr0)) * nx + ex;
-          T kv[NV], mv[NV], out[NV];
+        // ---- phase A: element contributions (UA elements per iteration) ----
+        for (int qb = threadIdx.x; qb < nse; qb += UA * BLOCK) {
+          T kv[UA][NV], mv[UA][NV], out[UA][NV];
+          typename TensorOf<T, DIM>::type D[UA];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const int o = base + ((v >> 2) & 1) * lay + ((v >> 1) & 1) * nx + (v & 1);
-            const T a = l0[o], b = l1[o];
-            kv[v] = kval(a, b);
-            mv[v] = mval(a, b);
-          }
-          if constexpr (DIM == 3) elem_apply_3d<T>(kv, mv, D, cxx, cyy, czz, cxy, cm, out);
-          else elem_apply_2d<T>(kv, mv, D, cxx, cyy, cm, out);
+          for (int h = 0; h < UA; ++h) {
+            const int q = qb + h * BLOCK;
+            const int qq = q < nse ? q : 0;
+            int lz = 0, rem = qq;
+            if constexpr (DIM == 3) {
+              lz = fdiv(qq, melay);
+              rem = qq - lz * elay;
+            }
+            const int r = fdiv(rem, mex);
+            const int ex = rem - r * EX;
+            const int ey = ey0 + r, ez = ez0 + lz;
+            D[h] = tensor_from<T, DIM>(ls[qq], lf + 3 * ((DIM == 3) ? lz : r), tau);
+            const int base = ((ez - kr0) * sy + (ey - jr0)) * nx + ex;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) lc[v * nse + q] = out[v];
+            for (int v = 0; v < NV; ++v) {
+              const int o = base + ((v >> 2) & 1) * lay + ((v >> 1) & 1) * nx + (v & 1);
+              const T a = l0[o], b = l1[o];
+              kv[h][v] = kval(a, b);
+              mv[h][v] = mval(a, b);
+            }
+          }
+#pragma unroll
+          for (int h = 0; h < UA; ++h) {
+            if constexpr (DIM == 3) elem_apply_3d<T>(kv[h], mv[h], D[h], cxx, cyy, czz, cxy, cm, out[h]);
+            else elem_apply_2d<T>(kv[h], mv[h], D[h], cxx, cyy, cm, out[h]);
+          }
+#pragma unroll
+          for (int h = 0; h < UA; ++h) {
+            const int q = qb + h * BLOCK;
+            if (q < nse) {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) lc[v * nse + q] = out[h][v];
+            }
+          }
         }
         __syncthreads();
         STM_T1P(t_pa, 7);
@@ -476,7 +505,7 @@ struct Team {
   __device__ void jacobi(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out,
                          TI om) const {
     const int n = L->g[l].n;
-    bytes += (x ? 5.0 : 4.0) * sizeof(TI) * n + (x ? dbytes(l) : 0.0);
+    bytes = uni(bytes + ((x ? 5.0 : 4.0) * sizeof(TI) * n + (x ? dbytes(l) : 0.0)));
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
       if (!x) {
@@ -507,6 +536,7 @@ struct Team {
           [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
       return;
     }
+    if constexpr (!MG) return;
     if (!x) {
       for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = om * b[idx] / diag_coarse(l, idx);
     } else {
@@ -521,7 +551,7 @@ struct Team {
 
   __device__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
     const int n = L->g[l].n;
-    bytes += 4.0 * sizeof(TI) * n + dbytes(l);
+    bytes = uni(bytes + (4.0 * sizeof(TI) * n + dbytes(l)));
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
       staged<TI>(
@@ -529,6 +559,7 @@ struct Team {
           [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
       return;
     }
+    if constexpr (!MG) return;
     for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = b[idx] - apply_coarse(l, x, idx, nullptr);
     __syncthreads();
   }
@@ -537,7 +568,7 @@ struct Team {
   __device__ void restrict_to(int l, const TI* __restrict__ rf, TI* __restrict__ bc) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
-    bytes += double(sizeof(TI)) * (gf.n + gc.n);
+    bytes = uni(bytes + (double(sizeof(TI)) * (gf.n + gc.n)));
     for (int idx = threadIdx.x; idx < gc.n; idx += BLOCK) {
       int I, J, K;
       decode<DIM>(gc, idx, I, J, K);
@@ -570,7 +601,7 @@ struct Team {
   __device__ void prolong_add(int l, const TI* __restrict__ xc, TI* __restrict__ xf) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
-    bytes += double(sizeof(TI)) * (2.0 * gf.n + gc.n);
+    bytes = uni(bytes + (double(sizeof(TI)) * (2.0 * gf.n + gc.n)));
     for (int idx = threadIdx.x; idx < gf.n; idx += BLOCK) {
       int i, j, k;
       decode<DIM>(gf, idx, i, j, k);
@@ -598,6 +629,13 @@ struct Team {
   // out = V-cycle(b) on grid 0.  Sweep s of a level writes buf[(s-1) % 2];
   // buf[1] is the level's output, so results land in place for any count.
   __device__ void vcycle(const TI* __restrict__ b0, TI* __restrict__ out0) const {
+    if constexpr (!MG) {
+      TI* buf[2] = {mgT(0), out0};
+      const int nc = L->sweeps;
+      jacobi(0, b0, nullptr, buf[0], wgt(0, 0));
+      for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[s % 2], buf[(s - 1) % 2], wgt(0, s - 1));
+      return;
+    }
     const int nmg = L->nmg;
     const int nu = prm.smooth_steps;
     for (int l = 0; l < nmg - 1; ++l) {
@@ -612,7 +650,7 @@ struct Team {
       const int l = nmg - 1;
       TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
       const TI* b = (l == 0) ? b0 : mgB(l);
-      const int nc = prm.coarse_sweeps;
+      const int nc = L->sweeps;
       jacobi(l, b, nullptr, buf[0], wgt(l, 0));
       for (int s = 2; s <= nc; ++s) jacobi(l, b, buf[s % 2], buf[(s - 1) % 2], wgt(l, s - 1));
     }
@@ -653,7 +691,7 @@ struct Team {
               nn[0] += double(y) * double(y);
               nn[1] += double(xown) * double(xown);
             });
-      } else {
+      } else if constexpr (MG) {
         for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
           TI d;
           const TI ax = apply_coarse(l, x0, idx, &d);
@@ -677,7 +715,7 @@ struct Team {
         __syncthreads();
       }
     }
-    bytes += prm.power_iters * (5.0 * sizeof(TI) * g.n + dbytes(l));
+    bytes = uni(bytes + (prm.power_iters * (5.0 * sizeof(TI) * g.n + dbytes(l))));
     return lam;
   }
 };
@@ -694,7 +732,7 @@ __device__ inline void chebyshev_weights(double a, double b, int K, double* w) {
   }
 }
 
-template <typename TI, int DIM, int BLOCK>
+template <typename TI, int DIM, int BLOCK, bool MG>
 __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restrict__ levels,
                                                         const TeamTask* __restrict__ tasks, SolverParams prm) {
   constexpr int NW = BLOCK / kWave;
@@ -715,7 +753,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   const LevelDev* L = levels + task.level;
   const int tid = threadIdx.x;
 
-  Team<TI, DIM, BLOCK> tm;
+  Team<TI, DIM, BLOCK, MG> tm;
   tm.L = L;
   tm.prm = prm;
   tm.work = task.work;
@@ -752,8 +790,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   double* ubuf = reinterpret_cast<double*>(task.work + L->off_U);
 
   const int m = L->m;
-  const double dt = L->dt, inv_dt = 1.0 / L->dt;
-  const double kr = prm.k_react, ar = prm.a_react, tau = prm.tau, thr = prm.threshold;
+  const double dt = uni(L->dt), inv_dt = uni(1.0 / L->dt);
+  const double kr = uni(prm.k_react), ar = uni(prm.a_react), tau = uni(prm.tau), thr = uni(prm.threshold);
   const int restart = prm.restart;
 
   bool have_prev = false;
@@ -770,7 +808,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     else if (have_prev) W = prevU;
 
     // ---- per-sample setup: coarse element tensors (averages of children; G == 1) ----
-    for (int l = 1; l < L->nmg; ++l) {
+    for (int l = 1; l < (MG ? L->nmg : 1); ++l) {
       const GridDev& gc = L->g[l];
       const GridDev& gf = L->g[l - 1];
       TI* Dc = tm.mgD(l);
@@ -814,7 +852,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     }
     // diagonal of the stiffness matrix on grid 0 (sigma is fixed for the sample),
     // initial state, activation markers, warm-start history
-    tm.bytes += (16.0 + sizeof(TI) + 24.0) * n0;
+    tm.bytes = uni(tm.bytes + ((16.0 + sizeof(TI) + 24.0) * n0));
     for (int q = tid; q < nb; q += BLOCK) {
       const int idx = tm.bidx(q);
       int i, j, k;
@@ -845,7 +883,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     for (int k = 0; k < m; ++k) {
       // ---- initial iterate of slab k ----
       const double* Wk = W ? W + (int64_t)k * n0 : nullptr;
-      tm.bytes += (Wk ? 40.0 : 16.0) * n0;
+      tm.bytes = uni(tm.bytes + ((Wk ? 40.0 : 16.0) * n0));
       for (int q = tid; q < nb; q += BLOCK) {
         const int idx = tm.bidx(q);
         if (Wk) {
@@ -868,8 +906,8 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         TI* w0 = tm.mgW(0);
         double rr[1] = {0.0};
         STM_T0(t_res);
-        tm.bytes += 24.0 * n0 + 8.0 * g0.ne + 3.0 * sizeof(TI) * n0;
-        for (int l = 1; l < L->nmg; ++l) tm.bytes += (8.0 + sizeof(TI)) * L->g[l].n;
+        tm.bytes = uni(tm.bytes + (24.0 * n0 + 8.0 * g0.ne + 3.0 * sizeof(TI) * n0));
+        for (int l = 1; l < L->nmg; ++l) tm.bytes = uni(tm.bytes + ((8.0 + sizeof(TI)) * L->g[l].n));
         {
           TI* __restrict__ di = tm.dinv;
           const double cmd = (DIM == 3) ? 8.0 * g0.hx * g0.hy * g0.hz / 216.0 : 4.0 * g0.hx * g0.hy / 36.0;
@@ -885,7 +923,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 rr[0] += r * r;
               });
         }
-        for (int l = 1; l < L->nmg; ++l) {  // G == 1 here
+        for (int l = 1; l < (MG ? L->nmg : 1); ++l) {  // G == 1 here
           const GridDev& gc = L->g[l];
           TI* wl = tm.mgW(l);
           const int st = 1 << l;
@@ -898,7 +936,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         }
         tm.template tsum<1>(rr);  // its barriers also publish the writes above
         STM_T1(t_res, 0);
-        const double beta = sqrt(rr[0]);
+        const double beta = uni(sqrt(rr[0]));
         if (!isfinite(beta)) {
           status = -5;
           break;
@@ -910,12 +948,12 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         }
         // ---- smoother weights: once per sample, from the first slab operator ----
         if (!weights_ready) {
-          for (int l = 0; l < L->nmg; ++l) {
+          for (int l = 0; l < (MG ? L->nmg : 1); ++l) {
             TI* x0 = (l == 0) ? tm.V + vs : tm.mgX(l);
             TI* x1 = (l == 0) ? tm.V + 2 * vs : tm.mgT(l);
             const double lmax = 1.05 * tm.power_lmax(l, x0, x1);
-            const int K = (l == L->nmg - 1) ? prm.coarse_sweeps : prm.smooth_steps;
-            if (tid == 0) chebyshev_weights(lmax / prm.cheb_ratio, lmax, K, omega_tab + l * kMaxSweeps);
+            const int K = (l == L->nmg - 1) ? L->sweeps : prm.smooth_steps;
+            if (tid == 0) chebyshev_weights(lmax / L->cheb_ratio, lmax, K, omega_tab + l * kMaxSweeps);
           }
           __syncthreads();
           weights_ready = true;
@@ -927,7 +965,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           gv[0] = beta;
         }
         __syncthreads();
-        const double tol_abs = eta * beta;
+        const double tol_abs = uni(eta * beta);
         int jdim = 0;
         for (int j = 0; j < restart; ++j) {
           TI* Vj = tm.V + j * vs;
@@ -938,7 +976,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           STM_T1(t_vc, 1);
           STM_T0(t_pa);
           // pass A: ws = A Z_j (into V_{j+1})
-          tm.bytes += 3.0 * sizeof(TI) * n0 + tm.dbytes(0);
+          tm.bytes = uni(tm.bytes + (3.0 * sizeof(TI) * n0 + tm.dbytes(0)));
           tm.template staged<TI>(
               Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [](TI a, TI) { return a; },
               [](TI a, TI ww) { return ww * a; },
@@ -950,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
 #pragma unroll
           for (int q = 0; q < 9; ++q) d[q] = 0.0;
           const int nk0 = min(j + 1, 8);
-          tm.bytes += (1.0 + nk0) * sizeof(TI) * n0;
+          tm.bytes = uni(tm.bytes + ((1.0 + nk0) * sizeof(TI) * n0));
           {
             const TI* __restrict__ Vb = tm.V;
             const TI* __restrict__ Vr = Vn;
@@ -978,7 +1016,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           }
           for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
             const int nk = min(j + 1 - k0, 8);
-            tm.bytes += (1.0 + nk) * sizeof(TI) * n0;
+            tm.bytes = uni(tm.bytes + ((1.0 + nk) * sizeof(TI) * n0));
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0;
             for (int q = tid; q < nb; q += BLOCK) {
@@ -1002,7 +1040,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           STM_T0(t_pb);
           // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
           double nn[1] = {0.0};
-          tm.bytes += (j + 3.0) * sizeof(TI) * n0;
+          tm.bytes = uni(tm.bytes + ((j + 3.0) * sizeof(TI) * n0));
           // vectors in chunks of 4, all loads of a chunk issued before use
           for (int qb = tid; qb < nb; qb += BLOCK * 2) {
             double w[2];
@@ -1037,7 +1075,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             }
           }
           tm.template tsum<1>(nn);
-          const double hn = sqrt(nn[0]);
+          const double hn = uni(sqrt(nn[0]));
           if (tid == 0) {
             const double hj1 = sc[j] * hn;
             sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
@@ -1060,7 +1098,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           __syncthreads();
           STM_T1(t_pb, 4);
           jdim = j + 1;
-          const double resid = sh_resid;
+          const double resid = uni(sh_resid);
           if (!(resid > tol_abs) || !(hn > 0.0)) break;
         }
         krylov_total += jdim;
@@ -1076,7 +1114,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         // ---- u += sum_q y_q z_q (float64) over the owned nodes, max-norm of the step ----
         STM_T0(t_up);
         double dm = 0.0;
-        tm.bytes += double(jdim) * sizeof(TI) * n0 + 16.0 * n0;
+        tm.bytes = uni(tm.bytes + (double(jdim) * sizeof(TI) * n0 + 16.0 * n0));
         for (int qb = tid; qb < nb; qb += BLOCK * 2) {
           double dlt[2] = {0.0, 0.0}, uo[2];
           int ix[2];
@@ -1107,7 +1145,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             }
           }
         }
-        dmax = tm.tmax(dm);  // its barrier also publishes u to the other members
+        dmax = uni(tm.tmax(dm));  // its barrier also publishes u to the other members
         STM_T1(t_up, 5);
         const double ach = sh_resid / beta;
         if (!isfinite(dmax)) {
@@ -1128,19 +1166,19 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             break;
           }
         }
-        dprev = dmax;
-        eta = fmax(prm.gmres_rtol, fmin(1e-4, 0.01 * dmax));
+        dprev = uni(dmax);
+        eta = uni(fmax(prm.gmres_rtol, fmin(1e-4, 0.01 * dmax)));
       }
       if (status == -5) break;
       if (!conv && status == 0) status = -4;
       newton_total += it;
       newton_max_slab = max(newton_max_slab, it);
-      worst_final = fmax(worst_final, dmax);
+      worst_final = uni(fmax(worst_final, dmax));
 
       // ---- accept slab k: store, activation crossing, shift history ----
       double* Uk = Uout + (int64_t)k * n0;
       const double tk = k * dt;
-      tm.bytes += 40.0 * n0;
+      tm.bytes = uni(tm.bytes + (40.0 * n0));
       for (int q = tid; q < nb; q += BLOCK) {
         const int idx = tm.bidx(q);
         const double un = u[idx], up = uprev[idx];
@@ -1193,51 +1231,44 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
 // ---------------------------------------------------------------------------
 // host launcher
 // ---------------------------------------------------------------------------
-template <typename TI, int DIM, int BLOCK>
-static hipError_t launch_one(const LevelDev* levels, const TeamTask* tasks, int n_blocks, SolverParams prm,
-                             size_t lds, bool cooperative, hipStream_t st) {
-  auto kern = st_team_kernel<TI, DIM, BLOCK>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (cooperative) {
-    void* args[] = {(void*)&levels, (void*)&tasks, (void*)&prm};
-    return hipLaunchCooperativeKernel((const void*)kern, dim3(n_blocks), dim3(BLOCK), args, (unsigned)lds, st);
-  }
-  hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(BLOCK), lds, st, levels, tasks, prm);
-  return hipGetLastError();
-}
-
-template <typename TI, int DIM>
-static hipError_t launch_dim(const LevelDev* levels, const TeamTask* tasks, int n_blocks, SolverParams prm, int block,
-                             size_t lds, bool coop, hipStream_t st) {
+template <typename TI, int DIM, bool MG>
+static const void* kernel_for_block(int block) {
   switch (block) {
-    case 256: return launch_one<TI, DIM, 256>(levels, tasks, n_blocks, prm, lds, coop, st);
-    case 512: return launch_one<TI, DIM, 512>(levels, tasks, n_blocks, prm, lds, coop, st);
-    case 1024: return launch_one<TI, DIM, 1024>(levels, tasks, n_blocks, prm, lds, coop, st);
-    default: return hipErrorInvalidValue;
+    case 256: return (const void*)st_team_kernel<TI, DIM, 256, MG>;
+    case 512: return (const void*)st_team_kernel<TI, DIM, 512, MG>;
+    case 1024: return (const void*)st_team_kernel<TI, DIM, 1024, MG>;
+    default: return nullptr;
   }
 }
 
-hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_blocks,
-                              SolverParams prm, int block, size_t lds_bytes, bool cooperative, hipStream_t st) {
+template <int DIM>
+static const void* kernel_for_dim(bool fp32, bool mg, int block) {
+  if (fp32) return mg ? kernel_for_block<float, DIM, true>(block) : kernel_for_block<float, DIM, false>(block);
+  return mg ? kernel_for_block<double, DIM, true>(block) : kernel_for_block<double, DIM, false>(block);
+}
+
+static const void* solver_kernel(int dim, bool fp32, bool mg, int block) {
+  return dim == 2 ? kernel_for_dim<2>(fp32, mg, block) : kernel_for_dim<3>(fp32, mg, block);
+}
+
+hipError_t launch_team_solver(int dim, bool inner_fp32, bool mg, const LevelDev* levels, const TeamTask* tasks,
+                              int n_blocks, SolverParams prm, int block, size_t lds_bytes, bool cooperative,
+                              hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  if (dim == 2)
-    return inner_fp32 ? launch_dim<float, 2>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st)
-                      : launch_dim<double, 2>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st);
-  return inner_fp32 ? launch_dim<float, 3>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st)
-                    : launch_dim<double, 3>(levels, tasks, n_blocks, prm, block, lds_bytes, cooperative, st);
+  const void* f = solver_kernel(dim, inner_fp32, mg, block);
+  if (!f) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)&levels, (void*)&tasks, (void*)&prm};
+  if (cooperative) return hipLaunchCooperativeKernel(f, dim3(n_blocks), dim3(block), args, (unsigned)lds_bytes, st);
+  return hipLaunchKernel(f, dim3(n_blocks), dim3(block), args, lds_bytes, st);
 }
 
 // Co-resident workgroups per CU for a launch configuration (0 on error).
-int team_solver_occupancy(int dim, bool inner_fp32, int block, size_t lds_bytes) {
+int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t lds_bytes) {
   int nb = 0;
-  const void* f = nullptr;
-#define STM_OCC(TI, D, B) f = (const void*)st_team_kernel<TI, D, B>
-  if (dim == 2 && !inner_fp32) { if (block == 256) STM_OCC(double, 2, 256); else if (block == 512) STM_OCC(double, 2, 512); else STM_OCC(double, 2, 1024); }
-  if (dim == 2 && inner_fp32) { if (block == 256) STM_OCC(float, 2, 256); else if (block == 512) STM_OCC(float, 2, 512); else STM_OCC(float, 2, 1024); }
-  if (dim == 3 && !inner_fp32) { if (block == 256) STM_OCC(double, 3, 256); else if (block == 512) STM_OCC(double, 3, 512); else STM_OCC(double, 3, 1024); }
-  if (dim == 3 && inner_fp32) { if (block == 256) STM_OCC(float, 3, 256); else if (block == 512) STM_OCC(float, 3, 512); else STM_OCC(float, 3, 1024); }
-#undef STM_OCC
+  const void* f = solver_kernel(dim, inner_fp32, mg, block);
+  if (!f) return 0;
   if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds_bytes) != hipSuccess) return 0;
   return nb;

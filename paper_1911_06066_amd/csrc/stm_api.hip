@@ -36,6 +36,7 @@ struct stm_ctx {
   LevelDev* d_levels = nullptr;  // device copy of all LevelDev
   SolverParams prm{};
   bool inner_fp32 = false;
+  bool any_mg = false;           // some level has a multigrid hierarchy (selects the solver kernel)
   // growable device buffers
   void* work = nullptr;
   size_t work_bytes = 0;
@@ -146,6 +147,8 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
     const int nz = p.dim == 3 ? L.nz : 1;
     if (L.nx < 3 || L.ny < 3 || (p.dim == 3 && L.nz < 2) || L.m < 1)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
+    if (L.smooth_sweeps < 0 || L.smooth_sweeps > kMaxSweeps || !(L.cheb_ratio == 0 || L.cheb_ratio > 1))
+      return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": smooth_sweeps in 0..32, cheb_ratio 0 or > 1");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
     if ((int64_t)L.nx * L.ny * nz * std::max(L.nx, L.ny) >= (int64_t)1 << 32)
@@ -204,6 +207,8 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
     nz = cz;
   }
   d.nmg = nmg;
+  d.sweeps = lv.smooth_sweeps > 0 ? lv.smooth_sweeps : p.coarse_sweeps;
+  d.cheb_ratio = lv.cheb_ratio > 0 ? lv.cheb_ratio : p.cheb_ratio;
   d.ic_cx = p.ic_center[0];
   d.ic_cy = p.ic_center[1];
   d.ic_cz = p.dim == 3 ? p.ic_center[2] : 0.0;
@@ -377,7 +382,7 @@ stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
   hipError_t e = launch_fill_u32(ctr, 0u, (int64_t)(sync_bytes / 4), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "fill");
   if ((st = timed_begin(c))) return st;
-  e = launch_team_solver(c->p.dim, c->inner_fp32, c->d_levels, c->d_tasks, n_blocks, c->prm, block,
+  e = launch_team_solver(c->p.dim, c->inner_fp32, c->any_mg, c->d_levels, c->d_tasks, n_blocks, c->prm, block,
                          (size_t)c->stage_bytes, coop, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, coop ? "cooperative team solver launch" : "team solver launch");
   // the task table stays alive until the kernel has finished
@@ -401,7 +406,7 @@ int max_team(const stm_ctx* c, int level) {
 
 // Workgroups that can be resident at once for the solver configuration.
 int block_capacity(stm_ctx* c, int block) {
-  const int occ = team_solver_occupancy(c->p.dim, c->inner_fp32, block, (size_t)c->stage_bytes);
+  const int occ = team_solver_occupancy(c->p.dim, c->inner_fp32, c->any_mg, block, (size_t)c->stage_bytes);
   return std::max(1, occ) * c->n_cu;
 }
 
@@ -451,6 +456,7 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
       stm_destroy(c);
       return st;
     }
+    c->any_mg = c->any_mg || c->levels[l].dev.nmg > 1;
   }
   if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
     stm_destroy(c);

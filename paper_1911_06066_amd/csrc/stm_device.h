@@ -38,6 +38,8 @@ struct LevelDev {
   int m;
   double dt, T;
   int nmg;                      // multigrid grids (>= 1)
+  int sweeps;                   // Jacobi sweeps on the coarsest V-cycle grid
+  double cheb_ratio;            // Chebyshev interval ratio of the sweep weights
   GridDev g[kMaxMG];
   const double* fib;            // grid-0 fibre table: per element row (2D) / layer (3D): c^2, s^2, c s
   double ic_cx, ic_cy, ic_cz, ic_r2;

@@ -11,10 +11,12 @@ namespace stm {
 // One workgroup per TeamTask; lds_bytes: dynamic LDS of each workgroup
 // (staging tiles); cooperative: launch with guaranteed co-residency (needed
 // when any team has G > 1).
-hipError_t launch_team_solver(int dim, bool inner_fp32, const LevelDev* levels, const TeamTask* tasks, int n_blocks,
-                              SolverParams prm, int block, size_t lds_bytes, bool cooperative, hipStream_t st);
+// mg: some level of the launch has a multigrid hierarchy (nmg > 1).
+hipError_t launch_team_solver(int dim, bool inner_fp32, bool mg, const LevelDev* levels, const TeamTask* tasks,
+                              int n_blocks, SolverParams prm, int block, size_t lds_bytes, bool cooperative,
+                              hipStream_t st);
 // Co-resident solver workgroups per CU for a configuration (0 on error).
-int team_solver_occupancy(int dim, bool inner_fp32, int block, size_t lds_bytes);
+int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t lds_bytes);
 
 // sigma[s][e] = sigma_f0 * exp(sum_k modes[e][k] xi[s][k]) on the matrix cores.
 // split_fp16: operands split into fp16 hi/lo pairs, fp32 accumulation; else float64 MFMA.
