@@ -191,7 +191,7 @@ def main():
             "kl_modes": M,
             "precision": wl["precision"],
             "parallelism": "single GPU, one workgroup team per sample",
-            "smoother_per_level": [list(t) for t in tuning] if tuning else "defaults",
+            "smoother_per_level": [list(t[:2]) for t in tuning] if tuning else "defaults",
         },
         "dof_steps_per_s": dof_steps / (ms / 1e3),
         "roofline": {

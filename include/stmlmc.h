@@ -69,6 +69,9 @@ typedef struct {
   int m;
   int smooth_sweeps;          /* Jacobi sweeps on the level's coarsest V-cycle grid, 0 .. 32 */
   double cheb_ratio;          /* Chebyshev interval ratio, 0 or > 1 */
+  double team_seconds[16];    /* measured device seconds per sample with a team of g+1 workgroups
+                                 (0 = unknown); the MLMC scheduler's starting cost model, refined by
+                                 the measurements of every launch */
 } stm_level;
 
 /*

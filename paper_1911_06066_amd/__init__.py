@@ -61,6 +61,9 @@ def problem_from_workload(wl, **overrides):
         if t is not None:
             p.levels[i].smooth_sweeps = int(t[0])
             p.levels[i].cheb_ratio = float(t[1])
+            for g, sec in enumerate((t[2] if len(t) > 2 else None) or []):
+                if g < 16:
+                    p.levels[i].team_seconds[g] = float(sec)
     p.n_modes = wl["n_modes"]
     prec = overrides.pop("precision", wl.get("precision", "fp64"))
     p.precision = _lib.PRECISIONS[prec]

@@ -21,7 +21,8 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 
 class StmLevel(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("m", ctypes.c_int),
-                ("smooth_sweeps", ctypes.c_int), ("cheb_ratio", ctypes.c_double)]
+                ("smooth_sweeps", ctypes.c_int), ("cheb_ratio", ctypes.c_double),
+                ("team_seconds", ctypes.c_double * 16)]
 
 
 class StmProblem(ctypes.Structure):

@@ -1,4 +1,4 @@
-"""Per-level smoother tuner with a JSON cache.
+"""Per-level smoother and team-size tuner with a JSON cache.
 
 The slab operators M/dt + K - M diag f'(u) of a level have a spectrum set by
 h and dt, so the best Jacobi sweep count K and Chebyshev interval ratio differ
@@ -7,9 +7,12 @@ cut Krylov (and, through the inexact-Newton forcing, Newton) iterations.  The
 tuner solves a batch of samples of each level with every candidate (one
 workgroup per sample, as in the MLMC launch), keeps the candidate with the
 smallest mean workgroup-seconds per sample among those whose samples all
-converge, and writes the choice with its measurements to a JSON file.  The
-conductivity fields come from the level's KL modes with standard normal
-coefficients drawn from their own seed, not from the workload's samples.
+converge.  With that smoother it then measures the seconds per sample for
+teams of G workgroups (a sample's space-time solve split over G workgroups):
+the MLMC scheduler's starting cost model, refined by every later launch.
+Choices and measurements go to a JSON file.  The conductivity fields come
+from the level's KL modes with standard normal coefficients drawn from their
+own seed, not from the workload's samples.
 
     python -m paper_1911_06066_amd.autotune --workload mlmc3_2d --out tuning.json
 """
@@ -23,6 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
 CANDIDATES = [(8, 10.0), (10, 10.0), (12, 10.0), (14, 10.0), (16, 10.0), (16, 20.0), (20, 10.0), (24, 10.0)]
+TEAM_SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16)
+MAX_TEAM = 16
 
 
 def tuning_path(workload, precision):
@@ -80,13 +85,35 @@ def tune(wl, precision=None, samples=32, candidates=CANDIDATES, seed=4242, block
         entry["smooth_sweeps"] = best["smooth_sweeps"] if best else 0
         entry["cheb_ratio"] = best["cheb_ratio"] if best else 0.0
         entry["results"] = results
+        # seconds per sample against team size, with the chosen smoother
+        team = [0.0] * MAX_TEAM
+        if best:
+            gmax = max(1, min(MAX_TEAM, int(wl["levels"][l][1]) // 8))
+            tune_l = [None] * len(wl["levels"])
+            tune_l[l] = (best["smooth_sweeps"], best["cheb_ratio"])
+            for G in TEAM_SIZES:
+                if G > gmax:
+                    break
+                over = dict(precision=precision, level_tuning=tune_l, team_size=G, max_lanes=S * G)
+                if block:
+                    over["block_threads"] = block
+                ctx = Context(wl, **over)
+                sig = ctx.kl_synthesize(l, modes[l], xi)
+                try:
+                    _, st = ctx.st_solve(l, sig)
+                    team[G - 1] = sum(s["device_seconds"] for s in st) / len(st)
+                except Exception as e:
+                    log("level %d team %d: %s" % (l, G, e))
+                ctx.close()
+                log("level %d team %d: %.4f s per sample" % (l, G, team[G - 1]))
+        entry["team_seconds"] = team
         rec["levels"].append(entry)
     return rec
 
 
 def level_tuning(wl, precision=None, path=None):
-    """(sweeps, ratio) per level from a tuning file, or None when there is no
-    file or it was measured for other grids."""
+    """(sweeps, ratio, team_seconds) per level from a tuning file, or None
+    when there is no file or it was measured for other grids."""
     precision = precision or wl.get("precision", "fp64")
     path = path or tuning_path(wl["name"], precision)
     if not os.path.exists(path):
@@ -99,7 +126,7 @@ def level_tuning(wl, precision=None, path=None):
     for l, e in enumerate(rec["levels"]):
         if e["grid"] != list(wl["levels"][l]) or e["steps"] != int(wl["steps"][l]):
             return None
-        out.append((int(e["smooth_sweeps"]), float(e["cheb_ratio"])))
+        out.append((int(e["smooth_sweeps"]), float(e["cheb_ratio"]), list(e.get("team_seconds", []))))
     return out
 
 

@@ -53,8 +53,9 @@ struct stm_ctx {
   // phase timing
   hipEvent_t ev[2] = {nullptr, nullptr};
   stm_timings tm{};
-  // measured mean device seconds per sample of each level (0 = not measured yet)
-  double measured_cost[STM_MAX_LEVELS] = {0};
+  // measured mean device seconds per sample of each level with a team of G
+  // workgroups, tsec[level][G] (0 = not measured yet)
+  double tsec[STM_MAX_LEVELS][kMaxTeam + 1] = {};
   int stage_bytes = 48 * 1024;   // dynamic LDS per solver workgroup
 };
 
@@ -149,6 +150,9 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
     if (L.smooth_sweeps < 0 || L.smooth_sweeps > kMaxSweeps || !(L.cheb_ratio == 0 || L.cheb_ratio > 1))
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": smooth_sweeps in 0..32, cheb_ratio 0 or > 1");
+    for (int g = 0; g < 16; ++g)
+      if (!(L.team_seconds[g] >= 0 && std::isfinite(L.team_seconds[g])))
+        return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": team_seconds must be finite and >= 0");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
     if ((int64_t)L.nx * L.ny * nz * std::max(L.nx, L.ny) >= (int64_t)1 << 32)
@@ -401,7 +405,7 @@ stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
 int max_team(const stm_ctx* c, int level) {
   const LevelDev& d = c->levels[level].dev;
   if (d.nmg > 1) return 1;
-  return std::max(1, std::min(16, d.g[0].ny / 8));
+  return std::max(1, std::min(kMaxTeam, d.g[0].ny / 8));
 }
 
 // Workgroups that can be resident at once for the solver configuration.
@@ -457,6 +461,7 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
       return st;
     }
     c->any_mg = c->any_mg || c->levels[l].dev.nmg > 1;
+    for (int g = 1; g <= kMaxTeam; ++g) c->tsec[l][g] = std::max(0.0, c->p.levels[l].team_seconds[g - 1]);
   }
   if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
     stm_destroy(c);
@@ -640,52 +645,98 @@ struct Group {          // all fine or all coarse members of one MLMC level
   int mlmc_level;
   bool coarse;
   int n0, n1;           // samples [n0, n1) solved in this round
-  double cost;          // estimated workgroup-seconds per sample
+  double t[kMaxTeam + 1];  // device seconds per sample with a team of G workgroups (G = 1 .. gmax)
   int lanes;            // teams
   int G;                // workgroups per team
   int gmax;             // largest team the grid allows
 };
 
-// Team allocation for one persistent launch.  Pick the smallest makespan
-// target T such that the workgroups fit the budget, where a group whose
-// sample costs at most T runs one workgroup per team and floor(T / c)
-// samples in sequence per team (each warm-started from the previous), and a
-// group whose sample costs more gets teams of ceil(c / T) workgroups (at most
-// gmax) so that a sample still finishes near T.
-void allocate_lanes(std::vector<Group>& gs, int budget) {
-  double total = 0.0, floor_t = 0.0;
-  for (auto& g : gs) {
-    total += (g.n1 - g.n0) * g.cost;
-    floor_t = std::max(floor_t, g.cost / g.gmax);
-  }
-  double T = std::max(floor_t, total / std::max(budget, 1));
-  for (int iter = 0; iter < 400; ++iter) {
-    int used = 0;
-    for (auto& g : gs) {
-      const int N = g.n1 - g.n0;
-      if (N <= 0) {
-        g.lanes = 0;
-        g.G = 1;
-        continue;
-      }
-      if (g.cost <= T) {
-        g.G = 1;
-        const int per = std::max(1, (int)std::floor(T / g.cost + 1e-9));
-        g.lanes = (N + per - 1) / per;
-      } else {
-        g.G = std::min(g.gmax, (int)std::ceil(g.cost / T - 1e-9));
-        const int per = std::max(1, (int)std::floor(T * g.G / g.cost + 1e-9));
-        g.lanes = (N + per - 1) / per;
-      }
-      used += g.lanes * g.G;
+// Per-sample seconds of grid l for team sizes 1 .. gmax.  Measured values
+// (the problem's table, then every launch's own timings) are used where
+// known; the rest come from t(G) = t1 (a + (1 - a) / G), the part a of a
+// sample's time that does not shrink with the team (synchronisation, per-pass
+// overheads) fitted to the two measured sizes furthest apart, a = 0.15
+// without two, and t1 from the static model without any.
+void team_times(const stm_ctx* c, int l, int gmax, double* t) {
+  const LevelDev& d = c->levels[l].dev;
+  int g0 = 0, g1 = 0;
+  for (int g = 1; g <= gmax; ++g)
+    if (c->tsec[l][g] > 0) {
+      if (!g0) g0 = g;
+      g1 = g;
     }
-    if (used <= budget) return;
-    T *= 1.05;
+  double a = 0.15, t1 = 2e-8 * (double)(d.g[0].n + 3000) * d.m;
+  auto shape = [&](double aa, int g) { return aa + (1.0 - aa) / g; };
+  if (g0 && g1 > g0) {
+    // ratio r = t(g1) / t(g0) = shape(a, g1) / shape(a, g0), solved for a
+    const double r = c->tsec[l][g1] / c->tsec[l][g0];
+    const double p0 = 1.0 / g0, p1 = 1.0 / g1;
+    const double den = (1.0 - p1) - r * (1.0 - p0);
+    if (den != 0.0) a = std::min(1.0, std::max(0.0, (r * p0 - p1) / den));
   }
-  for (auto& g : gs) {  // budget too small for any balance: one workgroup per group
+  if (g0) t1 = c->tsec[l][g0] / shape(a, g0);
+  for (int g = 1; g <= gmax; ++g) t[g] = c->tsec[l][g] > 0 ? c->tsec[l][g] : t1 * shape(a, g);
+}
+
+// Team allocation for one persistent launch: the smallest makespan target T
+// (bisection) for which every group fits, each group taking the team size
+// that needs the fewest workgroups -- a team of G runs floor(T / t(G))
+// samples in sequence (each warm-started from the previous) -- and the
+// workgroups of all groups fit the co-resident budget.
+bool fit_lanes(std::vector<Group>& gs, double T, int budget) {
+  long used = 0;
+  for (auto& g : gs) {
+    const int N = g.n1 - g.n0;
+    g.lanes = 0;
     g.G = 1;
-    g.lanes = (g.n1 > g.n0) ? 1 : 0;
+    if (N <= 0) continue;
+    long best = -1;
+    for (int G = 1; G <= g.gmax; ++G) {
+      if (g.t[G] > T) continue;
+      const long per = std::max(1L, (long)std::floor(T / g.t[G] + 1e-9));
+      const long lanes = (N + per - 1) / per;
+      if (best < 0 || lanes * G < best) {
+        best = lanes * G;
+        g.G = G;
+        g.lanes = (int)lanes;
+      }
+    }
+    if (best < 0) return false;
+    used += best;
   }
+  return used <= budget;
+}
+
+void allocate_lanes(std::vector<Group>& gs, int budget) {
+  double lo = 0.0, hi = 0.0;
+  for (auto& g : gs) {
+    if (g.n1 <= g.n0) continue;
+    double tmin = g.t[1];
+    for (int G = 2; G <= g.gmax; ++G) tmin = std::min(tmin, g.t[G]);
+    lo = std::max(lo, tmin);
+    hi += (g.n1 - g.n0) * g.t[1];
+  }
+  if (hi <= 0.0) {
+    for (auto& g : gs) {
+      g.G = 1;
+      g.lanes = 0;
+    }
+    return;
+  }
+  hi = std::max(hi, lo);
+  if (!fit_lanes(gs, hi, budget)) {  // budget too small for any balance: one workgroup per group
+    for (auto& g : gs) {
+      g.G = 1;
+      g.lanes = (g.n1 > g.n0) ? 1 : 0;
+    }
+    return;
+  }
+  for (int it = 0; it < 60 && hi - lo > 1e-4 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (fit_lanes(gs, mid, budget)) hi = mid;
+    else lo = mid;
+  }
+  fit_lanes(gs, hi, budget);
 }
 
 }  // namespace
@@ -790,20 +841,13 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         g.coarse = cm == 1;
         g.n0 = Ndone[l];
         g.n1 = Ntarget[l];
-        const LevelDev& d = c->levels[g.grid].dev;
-        // model: nodes x steps plus a per-slab overhead (small grids are
-        // dominated by the per-pass synchronisation); measured costs win
-        g.cost = 2e-8 * (double)(d.g[0].n + 3000) * d.m;
         g.lanes = 0;
         g.G = 1;
         g.gmax = max_team(c, g.grid);
+        team_times(c, g.grid, g.gmax, g.t);
         gs.push_back(g);
       }
     }
-    bool all_measured = true;
-    for (auto& g : gs) all_measured = all_measured && c->measured_cost[g.grid] > 0;
-    if (all_measured)
-      for (auto& g : gs) g.cost = c->measured_cost[g.grid];
     int block = 256;
     for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
     allocate_lanes(gs, std::min(lane_budget, block_capacity(c, block)));
@@ -834,20 +878,23 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       }
     }
     if ((st = run_tasks(c, tasks, block))) return st;
-    // measured workgroup-seconds per sample of each grid (cost model of later calls)
+    // measured seconds per sample of each grid at the team sizes used (the
+    // cost model of later calls)
     {
       std::vector<SampleStatsDev> tmp(nst);
       STM_HIP(c, hipMemcpy(tmp.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
-      std::vector<double> acc(L1, 0.0), cnt(L1, 0.0);
+      std::vector<double> acc(L1 * (kMaxTeam + 1), 0.0), cnt(L1 * (kMaxTeam + 1), 0.0);
       for (auto& g : gs) {
         const size_t base = g.coarse ? off_stc[g.mlmc_level] : off_stf[g.mlmc_level];
         for (int i = g.n0; i < g.n1; ++i) {
-          acc[g.grid] += tmp[base + i].ticks * 1e-8 * g.G;
-          cnt[g.grid] += 1.0;
+          acc[g.grid * (kMaxTeam + 1) + g.G] += tmp[base + i].ticks * 1e-8;
+          cnt[g.grid * (kMaxTeam + 1) + g.G] += 1.0;
         }
       }
       for (int l = 0; l < L1; ++l)
-        if (cnt[l] > 0) c->measured_cost[l] = acc[l] / cnt[l];
+        for (int G = 1; G <= kMaxTeam; ++G)
+          if (cnt[l * (kMaxTeam + 1) + G] > 0)
+            c->tsec[l][G] = acc[l * (kMaxTeam + 1) + G] / cnt[l * (kMaxTeam + 1) + G];
     }
     for (int l = 0; l < L1; ++l) Ndone[l] = std::max(Ndone[l], Ntarget[l]);
     // 3) statistics over all samples so far
@@ -899,8 +946,12 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       }
     }
     STM_HIP(c, hipMemcpy(sh.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
-    for (int l = 0; l < L1; ++l)  // workgroup-seconds per sample pair of the level
-      cost[l] = c->measured_cost[l] + (l > 0 ? c->measured_cost[l - 1] : 0.0);
+    for (int l = 0; l < L1; ++l) {  // workgroup-seconds per sample pair of the level
+      double tf[kMaxTeam + 1], tc[kMaxTeam + 1];
+      team_times(c, l, 1, tf);
+      if (l > 0) team_times(c, l - 1, 1, tc);
+      cost[l] = tf[1] + (l > 0 ? tc[1] : 0.0);
+    }
     if (!adaptive) break;
     // 4) Giles allocation: N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k))
     double ssum = 0.0;

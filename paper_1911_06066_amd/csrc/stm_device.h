@@ -10,6 +10,7 @@ namespace stm {
 constexpr int kMaxMG = 8;        // multigrid grids per MLMC level
 constexpr int kMaxRestart = 30;  // Krylov dimension limit
 constexpr int kWave = 64;
+constexpr int kMaxTeam = 16;  // largest team of workgroups per sample
 
 // One structured grid: nodes per axis, elements per axis, spacing.
 struct GridDev {
