@@ -106,6 +106,64 @@ def cpu_baseline(wl, modes, N, total_dof_steps, budget_s):
     }
 
 
+def compare_paths(wl, N, modes, xi, fp64_value):
+    """The same MLMC estimate (same samples, so the same RMSE) through
+
+    * the batched mixed-precision path: one persistent launch, float32 Krylov
+      and multigrid vectors and split-f16 KL inside float64 Newton;
+    * the plain float64 single-sample path: one stm_st_solve call per sample
+      (the library picks the sample's team), timed on a few samples of each
+      level and scaled to the workload's sample counts.
+
+    Outside the timed region of the main measurement.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1911_06066_amd import Context, autotune
+
+    out = {}
+    wlm = dict(wl, precision="mixed")
+    tun = autotune.level_tuning(wl, "mixed")
+    ctx = Context(wlm, **({"level_tuning": tun} if tun else {}))
+    ctx.mlmc_estimate(N, modes, xi)
+    torch.cuda.synchronize()
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.mlmc_estimate(N, modes, xi)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    mixed_value = float(sum(N)) / (ms / 1e3)
+    out["mixed_batched"] = {"value": mixed_value, "ms_per_step": ms,
+                            "smoother_per_level": [list(t[:2]) for t in tun] if tun else "defaults"}
+    # plain float64, one sample per call
+    ctx1 = Context(wl)
+    per = []
+    k = 3
+    for l in range(len(N)):
+        tl = 0.0
+        for lv in ([l, l - 1] if l > 0 else [l]):
+            sig = ctx1.kl_synthesize(lv, modes[lv], xi[l][:k].contiguous())
+            ctx1.st_solve(lv, sig[:1].contiguous(), stats=False)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(k):
+                u, _ = ctx1.st_solve(lv, sig[i:i + 1].contiguous(), stats=False)
+                ctx1.activation_map(lv, u)
+            torch.cuda.synchronize()
+            tl += (time.perf_counter() - t0) / k
+        per.append(tl)
+    total = float(np.dot(per, N))
+    single_value = float(sum(N)) / total
+    out["fp64_single_sample"] = {"value": single_value, "seconds_per_pair": per,
+                                 "sample": "%d pairs per level, one st_solve call per sample, scaled to N" % k}
+    out["mixed_batched_over_fp64_single"] = mixed_value / single_value
+    out["fp64_batched_over_fp64_single"] = fp64_value / single_value
+    out["mixed_batched_over_fp64_batched"] = mixed_value / fp64_value
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +175,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0 = skip)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the per-level smoother tuning file")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time the batched mixed-precision path and the single-sample float64 path (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -213,6 +273,8 @@ def main():
             "V": out["V"], "cost_s": out["cost"],
         },
     }
+    if args.compare and wl["precision"] == "fp64":
+        line["detail"]["comparison"] = compare_paths(wl, N, modes, xi, value)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(wl, modes_h, N, dof_steps, args.cpu_budget)
     print(json.dumps(line), flush=True)

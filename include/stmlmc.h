@@ -104,8 +104,9 @@ typedef struct {
   double gmres_rtol;          /* relative Krylov residual: 1e-10 (fp64), 1e-5 (mixed) */
   int gmres_restart;          /* Krylov dimension of one linear solve: 16, at most 30; an unfinished
                                  solve is continued by the next Newton step */
-  int mg_levels;              /* multigrid grids of the V-cycle: 1 (smoothing on the level's grid only);
-                                 -1: as deep as the grid allows (coarsest >= 5 nodes per axis) */
+  int mg_levels;              /* multigrid grids of the V-cycle: 1 (smoothing on the level's grid only).
+                                 Other values (-1: as deep as the grid allows) are rejected with
+                                 STM_E_UNSUPPORTED: the multi-grid kernel variant is disabled */
   int smooth_steps;           /* weighted-Jacobi sweeps before and after the coarse correction: 2 */
   double smooth_omega;        /* fixed Jacobi weight (smoother 0): 0.7 */
   int coarse_sweeps;          /* weighted-Jacobi sweeps on the coarsest grid (the only grid when
@@ -119,6 +120,12 @@ typedef struct {
   int max_lanes;              /* workgroups per solver launch: 1024 (capped by co-residency) */
   int team_size;              /* workgroups per sample in stm_st_solve: 0 = chosen from S and the
                                  device; >1 only with mg_levels = 1 */
+  double theta;               /* weight of the new time level in the diffusion term, in [1/2, 1]:
+                                 1 (default; 0 selects it) backward Euler, 1/2 the paper's
+                                 Crank-Nicolson (Sec. 3.2, eq. st-system: A = M + dt/2 K,
+                                 B = -M + dt/2 K); the reaction is always taken at the new level
+                                 (Sec. 3.3, eq. mono_disc).  Slab k solves
+                                 M (u_k - u_{k-1})/dt + K (theta u_k + (1-theta) u_{k-1}) - M f(u_k) = 0 */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */

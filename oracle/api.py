@@ -30,7 +30,7 @@ def level_problem(wl, level, **kw):
     args = dict(
         grid=g, m=wl["steps"][level], T=wl["T"], u0=initial_state(wl, g),
         k_react=wl["k_react"], a_react=wl["a_react"], sigma_f0=wl["sigma_f0"],
-        transverse_ratio=wl["transverse_ratio"], fiber_law=wl["fiber_law"],
+        transverse_ratio=wl["transverse_ratio"], fiber_law=wl["fiber_law"], theta=wl.get("theta", 1.0),
     )
     args.update(kw)
     return spacetime.STProblem(**args)

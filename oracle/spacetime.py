@@ -4,18 +4,25 @@ The paper discretises the monodomain equation (Sec. 2.1, eq. monodomain with
 the cubic FitzHugh-Nagumo ionic current of eq. ionic_term) by Q1 in space and
 a one-step scheme in time, and assembles all time steps into one block
 lower-bidiagonal space-time system C u = f (Sec. 3.2, eq. system_C).  The
-reaction enters as r(u) = dt (I (x) M_h) I_ion(u) with nodal evaluation of the
-ionic current (Sec. 3.3, eq. mono_disc) and the Jacobian is
-J = C + dt (I_m (x) M_h) diag(I_ion'(u)).  The workloads here use backward
-Euler steps and write the reaction as a source f(u) = -I_ion(u) =
-k u (u - a)(1 - u); dividing every block row by dt gives, for k = 1..m,
+paper's scheme is Crank-Nicolson for the diffusion, diagonal blocks
+A = M + dt/2 K and sub-diagonal blocks B = -M + dt/2 K (Sec. 3.2,
+eq. st-system); the reaction enters as r(u) = dt (I (x) M_h) I_ion(u) with
+nodal evaluation of the ionic current at the block row's own time level
+(Sec. 3.3, eq. mono_disc), and the Jacobian is
+J = C + dt (I_m (x) M_h) diag(I_ion'(u)).  With the reaction written as a
+source f(u) = -I_ion(u) = k u (u - a)(1 - u), a weight theta of the new time
+level in the diffusion term (theta = 1/2: the paper's Crank-Nicolson;
+theta = 1: backward Euler, the workloads' default), and every block row
+divided by dt, for k = 1..m
 
-    R_k(U) = M (u_k - u_{k-1}) / dt + K u_k - M f(u_k) - b_k = 0,
+    R_k(U) = M (u_k - u_{k-1}) / dt + K (theta u_k + (1 - theta) u_{k-1})
+             - M f(u_k) - b_k = 0,
 
-with u_0 the initial state and b_k the load vector of an optional external
-source s(x, t_k) (used only by manufactured-solution tests).  The Jacobian has
-diagonal blocks A_k = M / dt + K - M diag f'(u_k) and sub-diagonal blocks
--M / dt.  Newton's method (Sec. 3.5) solves the system; each linear solve is
+with u_0 the initial state and b_k = theta l(t_k) + (1 - theta) l(t_{k-1})
+the weighted load vector of an optional external source s(x, t) (used only
+by manufactured-solution tests).  The Jacobian has diagonal blocks
+A_k = M / dt + theta K - M diag f'(u_k) and sub-diagonal blocks
+-M / dt + (1 - theta) K.  Newton's method (Sec. 3.5) solves the system; each linear solve is
 done by sparse LU -- of the assembled space-time matrix, or block by block in
 forward substitution (the same exact solve of a block lower-bidiagonal
 matrix).  A time-stepping mode (Newton per slab) reaches the same discrete
@@ -68,6 +75,7 @@ class STProblem:
     source: object = None
     newton_atol: float = 1e-12
     newton_max: int = 50
+    theta: float = 1.0  # weight of the new time level in the diffusion term
     _cache: dict = field(default_factory=dict, repr=False)
 
     @property
@@ -109,26 +117,42 @@ class STProblem:
         return b
 
 
+def source_term(prob, k):
+    """b_k = theta l(t_k) + (1 - theta) l(t_{k-1}), 1-based slab index k."""
+    th, dt = prob.theta, prob.dt
+    b = th * prob.load(k * dt)
+    if th != 1.0:
+        b = b + (1.0 - th) * prob.load((k - 1) * dt)
+    return b
+
+
 def residual(prob, K, U):
-    """R[k-1] = M (u_k - u_{k-1})/dt + K u_k - M f(u_k) - b_k, k = 1..m; U (m, n)."""
+    """R[k-1] = M (u_k - u_{k-1})/dt + K (theta u_k + (1 - theta) u_{k-1})
+    - M f(u_k) - b_k, k = 1..m; U (m, n)."""
     M = prob.mass()
-    dt = prob.dt
+    dt, th = prob.dt, prob.theta
     R = np.empty_like(U)
     prev = prob.u0
     for k in range(prob.m):
         uk = U[k]
-        R[k] = (M @ (uk - prev)) / dt + K @ uk - M @ reaction(uk, prob.k_react, prob.a_react)
+        R[k] = ((M @ (uk - prev)) / dt + K @ (th * uk + (1.0 - th) * prev)
+                - M @ reaction(uk, prob.k_react, prob.a_react))
         if prob.source is not None:
-            R[k] -= prob.load((k + 1) * dt)
+            R[k] -= source_term(prob, k + 1)
         prev = uk
     return R
 
 
 def slab_matrix(prob, K, uk):
-    """A_k = M/dt + K - M diag f'(u_k)."""
+    """A_k = M/dt + theta K - M diag f'(u_k)."""
     M = prob.mass()
     fp = reaction_prime(uk, prob.k_react, prob.a_react)
-    return (M / prob.dt + K - M @ sp.diags(fp)).tocsc()
+    return (M / prob.dt + prob.theta * K - M @ sp.diags(fp)).tocsc()
+
+
+def sub_matrix(prob, K):
+    """B = -M/dt + (1 - theta) K, the block coupling slab k to slab k-1."""
+    return (-prob.mass() / prob.dt + (1.0 - prob.theta) * K).tocsc()
 
 
 def jacobian(prob, K, U):
@@ -139,17 +163,17 @@ def jacobian(prob, K, U):
     for k in range(m):
         blocks[k][k] = slab_matrix(prob, K, U[k])
         if k > 0:
-            blocks[k][k - 1] = -M / prob.dt
+            blocks[k][k - 1] = sub_matrix(prob, K)
     return sp.bmat(blocks, format="csc")
 
 
 def _solve_block_forward(prob, K, U, R):
     """delta = -J^-1 R by forward substitution over the diagonal blocks."""
-    M = prob.mass()
+    B = sub_matrix(prob, K)
     delta = np.empty_like(U)
     prev = np.zeros(prob.grid.n)
     for k in range(prob.m):
-        rhs = -R[k] + (M @ prev) / prob.dt
+        rhs = -R[k] - B @ prev
         delta[k] = spla.splu(slab_matrix(prob, K, U[k])).solve(rhs)
         prev = delta[k]
     return delta
@@ -207,15 +231,16 @@ def newton(prob, sigma, guess=None, mode="block"):
 
 def _newton_timestep(prob, K, guess):
     M = prob.mass()
-    dt = prob.dt
+    dt, th = prob.dt, prob.theta
     U = np.empty((prob.m, prob.grid.n))
     st = NewtonStats(converged=True)
     prev = prob.u0
     for k in range(prob.m):
         uk = prev.copy() if guess is None else np.array(guess[k], dtype=np.float64)
-        b = prob.load((k + 1) * dt) if prob.source is not None else 0.0
+        b = source_term(prob, k + 1) if prob.source is not None else 0.0
         for it in range(prob.newton_max):
-            r = (M @ (uk - prev)) / dt + K @ uk - M @ reaction(uk, prob.k_react, prob.a_react) - b
+            r = ((M @ (uk - prev)) / dt + K @ (th * uk + (1.0 - th) * prev)
+                 - M @ reaction(uk, prob.k_react, prob.a_react) - b)
             d = spla.splu(slab_matrix(prob, K, uk)).solve(-r)
             uk = uk + d
             st.iterations = max(st.iterations, it + 1)

@@ -65,6 +65,7 @@ def problem_from_workload(wl, **overrides):
                 if g < 16:
                     p.levels[i].team_seconds[g] = float(sec)
     p.n_modes = wl["n_modes"]
+    p.theta = wl.get("theta", 1.0)
     prec = overrides.pop("precision", wl.get("precision", "fp64"))
     p.precision = _lib.PRECISIONS[prec]
     for k, v in overrides.items():

@@ -53,6 +53,7 @@ class StmProblem(ctypes.Structure):
         ("block_threads", ctypes.c_int),
         ("max_lanes", ctypes.c_int),
         ("team_size", ctypes.c_int),
+        ("theta", ctypes.c_double),
     ]
 
 

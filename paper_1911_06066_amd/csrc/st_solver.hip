@@ -532,7 +532,7 @@ struct Team {
         return;
       }
       staged<TI>(
-          x, w, b, dinv, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+          x, w, b, dinv, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
           [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
       return;
     }
@@ -555,7 +555,7 @@ struct Team {
     if (l == 0) {
       const TI* __restrict__ w = mgW(0);
       staged<TI>(
-          x, w, b, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+          x, w, b, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
           [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
       return;
     }
@@ -626,14 +626,17 @@ struct Team {
     return TI(omega[l * kMaxSweeps + s]);
   }
 
-  // out = V-cycle(b) on grid 0.  Sweep s of a level writes buf[(s-1) % 2];
-  // buf[1] is the level's output, so results land in place for any count.
+  // out = V-cycle(b) on grid 0.  Pre- and post-smoothing sweeps alternate
+  // between a level's two buffers so that buf[1] is the level's output for any
+  // sweep count; the coarsest grid's sweeps start in the buffer that makes the
+  // last one land in buf[1].
   __device__ void vcycle(const TI* __restrict__ b0, TI* __restrict__ out0) const {
     if constexpr (!MG) {
+      // sweep s (1-based) of nc writes buf[(nc - s + 1) % 2]: the last one out0
       TI* buf[2] = {mgT(0), out0};
       const int nc = L->sweeps;
-      jacobi(0, b0, nullptr, buf[0], wgt(0, 0));
-      for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[s % 2], buf[(s - 1) % 2], wgt(0, s - 1));
+      jacobi(0, b0, nullptr, buf[nc % 2], wgt(0, 0));
+      for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[(nc - s + 2) % 2], buf[(nc - s + 1) % 2], wgt(0, s - 1));
       return;
     }
     const int nmg = L->nmg;
@@ -647,12 +650,13 @@ struct Team {
       restrict_to(l, buf[nu % 2], mgB(l + 1));
     }
     {
+      // coarsest grid: sweep s of nc writes buf[(nc - s + 1) % 2], the last buf[1]
       const int l = nmg - 1;
       TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
       const TI* b = (l == 0) ? b0 : mgB(l);
       const int nc = L->sweeps;
-      jacobi(l, b, nullptr, buf[0], wgt(l, 0));
-      for (int s = 2; s <= nc; ++s) jacobi(l, b, buf[s % 2], buf[(s - 1) % 2], wgt(l, s - 1));
+      jacobi(l, b, nullptr, buf[nc % 2], wgt(l, 0));
+      for (int s = 2; s <= nc; ++s) jacobi(l, b, buf[(nc - s + 2) % 2], buf[(nc - s + 1) % 2], wgt(l, s - 1));
     }
     for (int l = nmg - 2; l >= 0; --l) {
       TI* buf[2] = {mgT(l), l == 0 ? out0 : mgX(l)};
@@ -684,7 +688,7 @@ struct Team {
       if (l == 0) {
         const TI* __restrict__ w = mgW(0);
         staged<TI>(
-            x0, w, dinv, (const TI*)nullptr, [](TI a, TI) { return a; }, [](TI a, TI ww) { return ww * a; },
+            x0, w, dinv, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
             [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
               const TI y = ax * dio;
               x1[idx] = y;
@@ -792,6 +796,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   const int m = L->m;
   const double dt = uni(L->dt), inv_dt = uni(1.0 / L->dt);
   const double kr = uni(prm.k_react), ar = uni(prm.a_react), tau = uni(prm.tau), thr = uni(prm.threshold);
+  const double th = uni(prm.theta);
   const int restart = prm.restart;
 
   bool have_prev = false;
@@ -842,7 +847,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 a3 += Df[4 * fe + 3];
               }
             }
-        const double inv = 1.0 / (4 * cz);
+        const double inv = (l == 1 ? prm.theta : 1.0) / (4 * cz);  // theta K on every coarse grid
         Dc[4 * e] = TI(a0 * inv);
         Dc[4 * e + 1] = TI(a1 * inv);
         Dc[4 * e + 2] = TI(a2 * inv);
@@ -912,14 +917,15 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           TI* __restrict__ di = tm.dinv;
           const double cmd = (DIM == 3) ? 8.0 * g0.hx * g0.hy * g0.hz / 216.0 : 4.0 * g0.hx * g0.hy / 36.0;
           tm.template staged<double>(
-              u, uprev, tm.kdiag0, (const double*)nullptr, [](double a, double) { return a; },
+              u, uprev, tm.kdiag0, (const double*)nullptr,
+              [th](double a, double b) { return th * a + (1.0 - th) * b; },
               [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
               [&](int idx, int i, int j, int k, double y, double uown, double, double kd, double) {
                 const double r = -y;
                 const double w = inv_dt - react_d(uown, kr, ar);
                 V0[idx] = TI(r);
                 w0[idx] = TI(w);
-                di[idx] = TI(1.0 / (kd + tm.nel0(i, j, k) * cmd * w));
+                di[idx] = TI(1.0 / (th * kd + tm.nel0(i, j, k) * cmd * w));
                 rr[0] += r * r;
               });
         }
@@ -978,7 +984,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           // pass A: ws = A Z_j (into V_{j+1})
           tm.bytes = uni(tm.bytes + (3.0 * sizeof(TI) * n0 + tm.dbytes(0)));
           tm.template staged<TI>(
-              Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [](TI a, TI) { return a; },
+              Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
               [](TI a, TI ww) { return ww * a; },
               [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { Vn[idx] = w; });
           STM_T1(t_pa, 2);
@@ -1241,10 +1247,12 @@ static const void* kernel_for_block(int block) {
   }
 }
 
+// The multi-grid kernel variant (MG = true) is not built: the library rejects
+// problems with more than one V-cycle grid.
 template <int DIM>
 static const void* kernel_for_dim(bool fp32, bool mg, int block) {
-  if (fp32) return mg ? kernel_for_block<float, DIM, true>(block) : kernel_for_block<float, DIM, false>(block);
-  return mg ? kernel_for_block<double, DIM, true>(block) : kernel_for_block<double, DIM, false>(block);
+  if (mg) return nullptr;
+  return fp32 ? kernel_for_block<float, DIM, false>(block) : kernel_for_block<double, DIM, false>(block);
 }
 
 static const void* solver_kernel(int dim, bool fp32, bool mg, int block) {

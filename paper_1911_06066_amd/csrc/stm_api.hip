@@ -140,6 +140,12 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
   if (p.coarse_sweeps < 0 || p.coarse_sweeps > kMaxSweeps || p.smooth_steps < 0 || p.smooth_steps > kMaxSweeps)
     return fail(c, STM_E_INVALID, "sweep counts must be in 0..32");
   if (p.smoother < 0 || p.smoother > 1) return fail(c, STM_E_INVALID, "smoother must be 0 or 1");
+  if (p.mg_levels != 0 && p.mg_levels != 1)
+    return fail(c, STM_E_UNSUPPORTED,
+                "mg_levels other than 1 is disabled: the multi-grid V-cycle kernel faulted once on the GPU "
+                "with no cause found yet; the single-grid preconditioner is the supported path");
+  if (!(p.theta == 0 || (p.theta >= 0.5 && p.theta <= 1.0)))
+    return fail(c, STM_E_INVALID, "theta must be 0 (default) or in [1/2, 1]");
   if (p.lds_kb < 0 || p.lds_kb > 160) return fail(c, STM_E_INVALID, "lds_kb must be in 0..160");
   if (p.block_threads != 0 && p.block_threads != 256 && p.block_threads != 512 && p.block_threads != 1024)
     return fail(c, STM_E_INVALID, "block_threads must be 0, 256, 512 or 1024");
@@ -176,6 +182,7 @@ void fill_defaults(stm_problem& p) {
   if (p.smooth_omega <= 0) p.smooth_omega = 0.7;
   if (p.coarse_sweeps <= 0) p.coarse_sweeps = 8;
   if (p.cheb_ratio <= 1) p.cheb_ratio = p.dim == 2 ? 10.0 : 30.0;
+  if (p.theta == 0) p.theta = 1.0;
   if (p.lds_kb <= 0) p.lds_kb = 144;
   if (p.mg_levels == 0) p.mg_levels = 1;
   if (p.max_lanes <= 0) p.max_lanes = 1024;
@@ -489,6 +496,7 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
   s.smoother = (c->p.smoother == 1) ? 0 : 1;  // kernel: 1 = Chebyshev weights, 0 = fixed
   s.cheb_ratio = c->p.cheb_ratio;
   s.power_iters = 10;
+  s.theta = c->p.theta;
   *out = c;
   return STM_OK;
 }

@@ -73,6 +73,7 @@ struct SolverParams {
   int smoother;         // 0: fixed weight omega; 1: Chebyshev-root weights over [lmax/ratio, lmax]
   double cheb_ratio;
   int power_iters;      // power iterations estimating lmax(D^-1 A) per sample and grid
+  double theta;         // weight of the new time level in the diffusion term (1: BE, 1/2: CN)
 };
 
 constexpr int kMaxSweeps = 32;

@@ -35,6 +35,7 @@ _COMMON_2D = dict(
     ic_center=(0.0, 0.0),
     ic_radius=0.1,
     threshold=0.5,
+    theta=1.0,  # time scheme: 1 backward Euler, 0.5 Crank-Nicolson
     ell=0.2,
     s2=0.1,
     kl_grid=(41, 41),
@@ -52,6 +53,7 @@ _COMMON_3D = dict(
     ic_center=(0.0, 0.0, 0.0),
     ic_radius=0.1,
     threshold=0.5,
+    theta=1.0,
     ell=0.15,
     s2=0.2,
     kl_grid=(21, 21, 6),

@@ -73,7 +73,7 @@ def test_struct_layouts_match_header(cname, pyname):
 
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("n_levels", 0), ("n_modes", 0), ("precision", 7), ("gmres_restart", 31),
-    ("block_threads", 100), ("fiber_law", 9),
+    ("block_threads", 100), ("fiber_law", 9), ("theta", 0.3), ("theta", 1.5),
 ])
 def test_invalid_problem_rejected_before_device_work(field, value):
     L, lib = _lib()
@@ -83,6 +83,15 @@ def test_invalid_problem_rejected_before_device_work(field, value):
     h = ctypes.c_void_p()
     st = lib.stm_create(ctypes.byref(p), None, ctypes.byref(h))
     assert st == -1 and not h.value
+
+
+def test_multigrid_variant_is_refused():
+    """More than one V-cycle grid is rejected as unsupported (-6), not run."""
+    L, lib = _lib()
+    from paper_1911_06066_amd import problem_from_workload
+    p = problem_from_workload(stinputs.workload("small_mc_2d"), mg_levels=-1)
+    h = ctypes.c_void_p()
+    assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -6 and not h.value
 
 
 def test_non_nested_levels_rejected():

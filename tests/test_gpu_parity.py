@@ -93,6 +93,22 @@ def test_st_solve_fp64_matches_oracle(torch_dev, shape, m, S):
     assert list(cen) == list(cen_ref)
 
 
+@pytest.mark.parametrize("sweeps", [1, 7, 9])
+def test_odd_and_single_sweep_counts_match_oracle(torch_dev, sweeps):
+    """The smoother's buffers alternate per sweep; any count leaves the
+    preconditioned vector where GMRES reads it."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[(33, 33)], steps=[24])
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl, level_tuning=[(sweeps, 10.0)])
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+
+
 def test_st_solve_small_mc_workload_grid(torch_dev):
     """The 33^2 x 64-step grid of the single-level workload, 2 samples."""
     torch, dev = torch_dev
@@ -189,6 +205,50 @@ def test_st_solve_3d_fp64_matches_oracle(torch_dev):
     t, cen = ctx.activation_map(0, u)
     t_ref, _ = oapi.activation_map(wl, 0, U_ref)
     assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson (the paper's time scheme)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,precision,G", [(2, "fp64", 1), (2, "fp64", 3), (3, "fp64", 1), (2, "mixed", 1)])
+def test_crank_nicolson_matches_oracle(torch_dev, dim, precision, G):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    if dim == 2:
+        wl = _wl(levels=[(33, 33)], steps=[24], theta=0.5, precision=precision)
+    else:
+        wl = stinputs.workload("slab3d", levels=[(9, 9, 5)], steps=[8], n_modes=8, kl_grid=(9, 9, 3),
+                               precision=precision, ic_radius=0.3, sigma_f0=4e-3, theta=0.5)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl, team_size=G)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    t, _ = ctx.activation_map(0, u)
+    t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+    if precision == "fp64":
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+    else:
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-6 * wl["T"]
+    # the scheme matters: backward Euler gives a measurably different solution
+    U_be, _ = oapi.st_solve(dict(wl, theta=1.0), 0, sig, mode="timestep")
+    assert _rel(U_be, U_ref) > 1e-6
+
+
+def test_crank_nicolson_mlmc_matches_oracle(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl, N, modes, xi = _mlmc_case("fp64")
+    wl = dict(wl, theta=0.5)
+    ctx = Context(wl)
+    out = ctx.mlmc_estimate(N, [torch.from_numpy(m).to(dev) for m in modes],
+                            [torch.from_numpy(x).to(dev) for x in xi])
+    ref = oapi.mlmc_estimate(wl, N, xi, modes, solve_mode="timestep")
+    assert np.abs(out["mean"].cpu().numpy() - ref["mean"]).max() <= 1e-9 * wl["T"]
+    np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8, atol=1e-15)
 
 
 # ---------------------------------------------------------------------------

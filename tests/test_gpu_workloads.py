@@ -221,6 +221,8 @@ def test_adaptive_sample_counts_follow_the_allocation_rule(torch_dev):
     assert np.abs(out["mean"].cpu().numpy() - lm.sum(axis=0)).max() <= 1e-12 * T
 
 
+@pytest.mark.skip(reason="the multi-grid kernel variant faulted the GPU once (memory aperture violation) "
+                         "with no cause found by reading the code; mg_levels > 1 is rejected until it is")
 @pytest.mark.parametrize("dim", [2, 3])
 def test_multigrid_vcycle_matches_oracle(torch_dev, dim):
     """The multigrid preconditioner (restriction, coarse operators from

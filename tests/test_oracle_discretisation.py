@@ -52,6 +52,47 @@ def test_cosine_mode_decays_exactly(shape, lengths):
         np.testing.assert_allclose(U[k], expect, rtol=0, atol=1e-13)
 
 
+# Crank-Nicolson (Sec. 3.2, eq. st-system: A = M + dt/2 K, B = -M + dt/2 K):
+# on a cosine mode each step multiplies by (1 - dt lam / 2) / (1 + dt lam / 2).
+@pytest.mark.parametrize("shape,lengths", [((17, 9), (1.0, 1.0)), ((9, 7, 5), (1.0, 1.0, 1.0))])
+def test_crank_nicolson_cosine_mode_amplification(shape, lengths):
+    g = Grid(shape, lengths)
+    x = g.nodes()
+    u0 = np.prod(np.cos(np.pi * x / np.array(lengths)), axis=1)
+    sigma_f0, ratio = 2e-2, 0.1
+    prob = _prob(g, 8, 0.5, u0, k_react=0.0, sigma_f0=sigma_f0, transverse_ratio=ratio, fiber_law="x", theta=0.5)
+    sigma = np.full(g.n_el, sigma_f0)
+    U, st = spacetime.newton(prob, sigma)
+    assert st.converged
+    D = [sigma_f0] + [ratio * sigma_f0] * (g.dim - 1)
+    lam = sum(_lam1d(D[a], g.h[a], lengths[a]) for a in range(g.dim))
+    amp = (1.0 - 0.5 * prob.dt * lam) / (1.0 + 0.5 * prob.dt * lam)
+    for k in range(prob.m):
+        np.testing.assert_allclose(U[k], u0 * amp ** (k + 1), rtol=0, atol=1e-13)
+
+
+def test_crank_nicolson_is_second_order_in_time():
+    """Against the semi-discrete solution exp(-lam t) u0 of a cosine mode: the
+    time error falls by 4 per halving of dt (2 for backward Euler)."""
+    g = Grid((17, 17), (1.0, 1.0))
+    x = g.nodes()
+    u0 = np.cos(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1])
+    sigma_f0 = 5e-2
+    lam = _lam1d(sigma_f0, g.h[0]) + _lam1d(0.1 * sigma_f0, g.h[1])
+    T = 1.0
+    errs = {}
+    for th in (0.5, 1.0):
+        errs[th] = []
+        for m in (8, 16, 32):
+            prob = _prob(g, m, T, u0, k_react=0.0, sigma_f0=sigma_f0, fiber_law="x", theta=th)
+            U, _ = spacetime.newton(prob, np.full(g.n_el, sigma_f0))
+            errs[th].append(np.abs(U[-1] - np.exp(-lam * T) * u0).max())
+    r_cn = [errs[0.5][i] / errs[0.5][i + 1] for i in range(2)]
+    r_be = [errs[1.0][i] / errs[1.0][i + 1] for i in range(2)]
+    assert all(3.8 < r < 4.2 for r in r_cn), r_cn
+    assert all(1.8 < r < 2.2 for r in r_be), r_be
+
+
 # ---------------------------------------------------------------------------
 # Stiffness on a linear field: (K u)_i equals the boundary flux integral
 # int_{dD} psi_i (D grad u) . n ds (Green's formula, D constant).  Pins the
@@ -144,17 +185,22 @@ def test_assembly_matches_brute_force(shape):
     np.testing.assert_allclose(fem.assemble_stiffness(g, D).toarray(), Kb, rtol=0, atol=1e-13)
 
 
-def test_newton_matches_generic_root_finder():
+@pytest.mark.parametrize("scheme", ["backward_euler", "crank_nicolson"])
+def test_newton_matches_generic_root_finder(scheme):
     """Full space-time Newton vs scipy.optimize.root on 36 unknowns, with the
-    residual written from brute-force dense matrices."""
+    residual written from brute-force dense matrices: backward Euler, and the
+    paper's Crank-Nicolson blocks A = M + dt/2 K, B = -M + dt/2 K with the
+    reaction dt M I_ion(u) at the new level."""
     g = Grid((3, 3), (1.0, 1.0))
     rng = np.random.default_rng(5)
     sigma = rng.uniform(0.02, 0.2, g.n_el)
     u0 = rng.uniform(0.0, 1.0, g.n)
-    prob = _prob(g, 4, 0.2, u0, fiber_law="diag2d")
+    cn = scheme == "crank_nicolson"
+    prob = _prob(g, 4, 0.2, u0, fiber_law="diag2d", theta=0.5 if cn else 1.0)
     theta = fem.fiber_angles(g, "diag2d")
     Mb, Kb = _brute_force(g, fem.diffusion_tensors(sigma, theta, prob.tau, 2))
     dt = prob.dt
+    A, B = Mb + 0.5 * dt * Kb, -Mb + 0.5 * dt * Kb
 
     def F(x):
         U = x.reshape(4, g.n)
@@ -162,7 +208,10 @@ def test_newton_matches_generic_root_finder():
         prev = u0
         for k in range(4):
             f = 8.0 * U[k] * (U[k] - 0.1) * (1.0 - U[k])
-            out.append(Mb @ (U[k] - prev) / dt + Kb @ U[k] - Mb @ f)
+            if cn:
+                out.append(A @ U[k] + B @ prev - dt * Mb @ f)
+            else:
+                out.append(Mb @ (U[k] - prev) / dt + Kb @ U[k] - Mb @ f)
             prev = U[k]
         return np.concatenate(out)
 
@@ -172,13 +221,14 @@ def test_newton_matches_generic_root_finder():
     np.testing.assert_allclose(U.ravel(), sol.x, rtol=0, atol=1e-12)
 
 
-def test_three_solve_modes_agree():
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_three_solve_modes_agree(theta):
     g = Grid((9, 9), (1.0, 1.0))
     rng = np.random.default_rng(11)
     sigma = 1e-3 * np.exp(0.3 * rng.standard_normal(g.n_el))
     x = g.nodes()
     u0 = ((x ** 2).sum(1) <= 0.3 ** 2).astype(float)
-    prob = _prob(g, 8, 1.0, u0, sigma_f0=1e-3)
+    prob = _prob(g, 8, 1.0, u0, sigma_f0=1e-3, theta=theta)
     out = [spacetime.newton(prob, sigma, mode=mode)[0] for mode in ("monolithic", "block", "timestep")]
     np.testing.assert_allclose(out[0], out[1], rtol=0, atol=1e-12)
     np.testing.assert_allclose(out[0], out[2], rtol=0, atol=1e-12)
