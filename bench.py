@@ -106,7 +106,7 @@ def cpu_baseline(wl, modes, N, total_dof_steps, budget_s):
     }
 
 
-def compare_paths(wl, N, modes, xi, fp64_value):
+def compare_paths(wl, N, modes, xi, fp64_value, fp64_out):
     """The same MLMC estimate (same samples, so the same RMSE) through
 
     * the batched mixed-precision path: one persistent launch, float32 Krylov
@@ -115,7 +115,10 @@ def compare_paths(wl, N, modes, xi, fp64_value):
       (the library picks the sample's team), timed on a few samples of each
       level and scaled to the workload's sample counts.
 
-    Outside the timed region of the main measurement.
+    The mixed estimate's deviation from the float64 one (max-norm of the
+    mean and variance fields, relative to their max-norm) is reported next
+    to the estimator's sampling error sqrt(sum_l V_l / N_l).  Outside the
+    timed region of the main measurement.
     """
     import numpy as np
     import torch
@@ -126,8 +129,16 @@ def compare_paths(wl, N, modes, xi, fp64_value):
     wlm = dict(wl, precision="mixed")
     tun = autotune.level_tuning(wl, "mixed")
     ctx = Context(wlm, **({"level_tuning": tun} if tun else {}))
-    ctx.mlmc_estimate(N, modes, xi)
+    mo = ctx.mlmc_estimate(N, modes, xi)
     torch.cuda.synchronize()
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    err = {"mean_rel_maxnorm": rel(mo["mean"], fp64_out["mean"]),
+           "var_rel_maxnorm": rel(mo["var"], fp64_out["var"]),
+           "mean_abs_maxnorm": float((mo["mean"] - fp64_out["mean"]).abs().max()),
+           "sampling_rmse": float(np.sqrt(sum(v / n for v, n in zip(fp64_out["V"], N))))}
     steps = 3
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -136,7 +147,8 @@ def compare_paths(wl, N, modes, xi, fp64_value):
     ms = (time.perf_counter() - t0) / steps * 1e3
     mixed_value = float(sum(N)) / (ms / 1e3)
     out["mixed_batched"] = {"value": mixed_value, "ms_per_step": ms,
-                            "smoother_per_level": [list(t[:2]) for t in tun] if tun else "defaults"}
+                            "smoother_per_level": [list(t[:2]) for t in tun] if tun else "defaults",
+                            "error_vs_fp64": err}
     # plain float64, one sample per call
     ctx1 = Context(wl)
     per = []
@@ -274,7 +286,7 @@ def main():
         },
     }
     if args.compare and wl["precision"] == "fp64":
-        line["detail"]["comparison"] = compare_paths(wl, N, modes, xi, value)
+        line["detail"]["comparison"] = compare_paths(wl, N, modes, xi, value, out)
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(wl, modes_h, N, dof_steps, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -57,6 +57,19 @@ typedef enum {
   STM_FIBER_DIAG = 3     /* theta = pi/4 */
 } stm_fiber_law;
 
+typedef enum {
+  STM_FIELD_LOGNORMAL = 0,  /* sigma = sigma_f0 exp(g) */
+  STM_FIELD_ADDITIVE = 1    /* sigma = sigma_f0 (1 + g): the paper's expansion G_0 + s sum sqrt(lambda_k)
+                               phi_k y_k (Sec. 2.2, eq. KL-expansion) with G_0 = sigma_f0 and the
+                               factor s G_0 folded into the modes; the caller keeps 1 + g > 0 */
+} stm_field_kind;
+
+typedef enum {
+  STM_IC_BALL = 0,   /* u(x, 0) = 1 in the closed ball |x - ic_center| <= ic_radius, else 0 */
+  STM_IC_GAUSS = 1   /* u(x, 0) = exp(-|x - ic_center|^2 / ic_radius^2): the paper's Gaussian
+                        stimulus (Sec. 4, "Parameters for the experiments"), in units of u_peak */
+} stm_ic_kind;
+
 #define STM_MAX_LEVELS 8
 
 /* One MLMC level: nodes per axis (nz = 1 in 2D, all odd) and time steps.
@@ -79,9 +92,11 @@ typedef struct {
  * [0,lx] x [0,ly] (x [0,lz]) with homogeneous Neumann boundaries, backward
  * Euler in time on [0,T], Q1 elements in space (Sec. 2.1, Sec. 3.2).
  *   f(u) = k_react u (u - a_react)(1 - u)       (FitzHugh-Nagumo cubic, eq. ionic_term)
- *   D_e  = sigma_e a a^T + transverse_ratio sigma_f0 (I - a a^T)
+ *   D_e  = sigma_e a a^T + tau_e (I - a a^T),
+ *          tau_e = transverse_ratio sigma_f0 (tau_relative = 0) or transverse_ratio sigma_e (= 1;
+ *          with transverse_ratio 1 the isotropic scalar field sigma_e I of Sec. 2.1)
  *   a    = (cos theta, sin theta[, 0]), theta from fiber_law at the element centroid
- *   u(x, 0) = 1 in the closed ball |x - ic_center| <= ic_radius, else 0
+ *   u(x, 0) from ic_kind (stm_ic_kind)
  * The activation map is the first time u reaches `threshold`.
  */
 typedef struct {
@@ -126,6 +141,9 @@ typedef struct {
                                  B = -M + dt/2 K); the reaction is always taken at the new level
                                  (Sec. 3.3, eq. mono_disc).  Slab k solves
                                  M (u_k - u_{k-1})/dt + K (theta u_k + (1-theta) u_{k-1}) - M f(u_k) = 0 */
+  int field_kind;             /* stm_field_kind of stm_kl_synthesize and stm_mlmc_estimate: 0 lognormal */
+  int tau_relative;           /* 0: tau_e = transverse_ratio sigma_f0; 1: tau_e = transverse_ratio sigma_e */
+  int ic_kind;                /* stm_ic_kind: 0 ball */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */
@@ -198,14 +216,15 @@ stm_status stm_get_timings(const stm_ctx* ctx, stm_timings* out);
 stm_status stm_level_size(const stm_ctx* ctx, int level, int* n_nodes, int* n_elements, int* m);
 
 /*
- * KL synthesis (Sec. 2.2, eq. KL-expansion in lognormal form):
- *   sigma[s][e] = sigma_f0 * exp( sum_k modes[e][k] * xi[s][k] ),
+ * KL synthesis (Sec. 2.2, eq. KL-expansion), with g[s][e] = sum_k modes[e][k] * xi[s][k]:
+ *   sigma[s][e] = sigma_f0 * exp(g[s][e])      (field_kind STM_FIELD_LOGNORMAL)
+ *   sigma[s][e] = sigma_f0 * (1 + g[s][e])     (field_kind STM_FIELD_ADDITIVE),
  * modes[E][M] (the eigenfunctions at the element centroids of `level`, each
- * column pre-scaled by sqrt(lambda_k)), xi[S][M], sigma[S][E]; E is the
- * element count of the level and M = n_modes.  Computed as one matrix product
- * on the matrix cores: float64 operands (STM_PREC_FP64) or split-fp16
- * operands with float32 accumulation (STM_PREC_MIXED; relative error of the
- * exponent about 1e-7).  S >= 0 (S = 0 is a no-op).
+ * column pre-scaled by sqrt(lambda_k), and by the damping s for the additive
+ * field), xi[S][M], sigma[S][E]; E is the element count of the level and
+ * M = n_modes.  Computed as one matrix product on the matrix cores: float64
+ * operands (STM_PREC_FP64) or split-fp16 operands with float32 accumulation
+ * (STM_PREC_MIXED; relative error of g about 1e-7).  S >= 0 (S = 0 is a no-op).
  */
 stm_status stm_kl_synthesize(stm_ctx* ctx, int level, const double* modes, const double* xi,
                              int S, double* sigma);

@@ -18,11 +18,16 @@ def level_grid(wl, level):
 
 
 def initial_state(wl, grid):
-    """u0 = 1 inside the closed ball |x - c| <= r, else 0."""
+    """u0 = 1 inside the closed ball |x - c| <= r, else 0 (ic_kind 'ball'); or the
+    Gaussian bump u0 = exp(-|x - c|^2 / r^2) (ic_kind 'gauss': the paper's
+    stimulus shape of Sec. 4, in units of u_peak, taken as the initial state)."""
     x = grid.nodes()
     c = np.asarray(wl["ic_center"], dtype=np.float64)[: grid.dim]
     r = wl["ic_radius"]
-    return (((x - c) ** 2).sum(axis=1) <= r * r).astype(np.float64)
+    d2 = ((x - c) ** 2).sum(axis=1)
+    if wl.get("ic_kind", "ball") == "gauss":
+        return np.exp(-d2 / (r * r))
+    return (d2 <= r * r).astype(np.float64)
 
 
 def level_problem(wl, level, **kw):
@@ -31,24 +36,39 @@ def level_problem(wl, level, **kw):
         grid=g, m=wl["steps"][level], T=wl["T"], u0=initial_state(wl, g),
         k_react=wl["k_react"], a_react=wl["a_react"], sigma_f0=wl["sigma_f0"],
         transverse_ratio=wl["transverse_ratio"], fiber_law=wl["fiber_law"], theta=wl.get("theta", 1.0),
+        tau_relative=bool(wl.get("tau_relative", 0)),
     )
     args.update(kw)
     return spacetime.STProblem(**args)
 
 
 def kl_basis(wl):
-    """Nystrom KL eigenpairs of the workload's covariance on its KL grid."""
+    """KL eigenpairs of the workload's covariance: Nystrom on its KL grid for
+    the exponential kernel; for the Gaussian kernel, the rank-M pivoted
+    Cholesky factor on the nodes of the KL grid (the finest mesh)."""
     g = Grid(wl["kl_grid"], wl["lengths"])
+    if wl.get("kernel", "exp") == "gauss":
+        return kl.PivotedCholeskyKL(g.nodes(), wl["sig_kl"], wl["n_modes"])
     return kl.NystromKL(g, wl["ell"], wl["s2"], wl["n_modes"])
 
 
+def kl_damping(wl, basis):
+    """The additive field's factor s (1 for the lognormal field)."""
+    if wl.get("field", "lognormal") != "additive":
+        return 1.0
+    return kl.damping(basis.modes(basis.pts), wl["kl_s"], wl["kl_delta"])
+
+
 def kl_modes(wl, level, basis=None):
-    """modes[e, k] = sqrt(lambda_k) phi_k(x_e) at the level's element centroids."""
+    """modes[e, k] = sqrt(lambda_k) phi_k(x_e) at the level's element centroids
+    (times the damping s for the additive field)."""
     basis = kl_basis(wl) if basis is None else basis
-    return basis.modes(level_grid(wl, level).centroids())
+    return basis.modes(level_grid(wl, level).centroids()) * kl_damping(wl, basis)
 
 
-def kl_synthesize(modes, xi, sigma_f0):
+def kl_synthesize(modes, xi, sigma_f0, field="lognormal"):
+    if field == "additive":
+        return kl.synthesize_additive(modes, xi, sigma_f0)
     return kl.synthesize_sigma(modes, xi, sigma_f0)
 
 
@@ -92,7 +112,7 @@ def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
     fine_q, coarse_q = [], []
 
     def level_qoi(lv, xi):
-        sig = kl_synthesize(modes_levels[lv], xi, wl["sigma_f0"])
+        sig = kl_synthesize(modes_levels[lv], xi, wl["sigma_f0"], wl.get("field", "lognormal"))
         U, _ = st_solve(wl, lv, sig, mode=solve_mode)
         t, _ = activation_map(wl, lv, U)
         g = level_grid(wl, lv)

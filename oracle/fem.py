@@ -72,13 +72,18 @@ def fiber_directions(theta, dim):
     return a
 
 
-def diffusion_tensors(sigma, theta, tau, dim):
-    """D_e = sigma_e a a^T + tau (I - a a^T), array (n_el, dim, dim)."""
+def diffusion_tensors(sigma, theta, tau, dim, tau_rel=0.0):
+    """D_e = sigma_e a a^T + (tau + tau_rel sigma_e) (I - a a^T), array (n_el, dim, dim).
+
+    tau_rel = 0: a constant transverse conductivity tau (the fibre model);
+    tau = 0, tau_rel = 1: the isotropic scalar field D_e = sigma_e I of the
+    paper's experiments (Sec. 2.1 takes G scalar and isotropic)."""
     sigma = np.asarray(sigma, dtype=np.float64)
     a = fiber_directions(theta, dim)
     aa = a[:, :, None] * a[:, None, :]
     eye = np.eye(dim)[None, :, :]
-    return sigma[:, None, None] * aa + tau * (eye - aa)
+    t = tau + tau_rel * sigma
+    return sigma[:, None, None] * aa + t[:, None, None] * (eye - aa)
 
 
 def fiber_angles(grid, law):

@@ -127,3 +127,100 @@ def synthesize_sigma(modes, xi, sigma_f0):
     xi = np.atleast_2d(np.asarray(xi, dtype=np.float64))
     g = xi @ modes.T
     return sigma_f0 * np.exp(g)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own random field (Sec. 2.2, eq. KL-expansion; Sec. 4, "Parameters
+# for KL expansion"): an additive expansion G = G_0 + s sum_k sqrt(lambda_k)
+# phi_k(x) y_k with y_k ~ U(-1, 1), the Gaussian correlation kernel
+# exp(-d^2 / sigma_KL), and the stochastic dimension M fixed by a low-rank
+# pivoted Cholesky factor of the covariance matrix on the mesh points.
+# ---------------------------------------------------------------------------
+
+
+def gauss_kernel(x, y, sig_kl):
+    """exp(-|x - y|^2 / sig_kl) for point sets x (p, d), y (q, d)."""
+    x = np.atleast_2d(x)
+    y = np.atleast_2d(y)
+    d2 = ((x[:, None, :] - y[None, :, :]) ** 2).sum(axis=2)
+    return np.exp(-d2 / sig_kl)
+
+
+class PivotedCholeskyKL:
+    """Rank-M pivoted Cholesky of the covariance matrix C_ij = k(x_i, x_j).
+
+    The factor is built one column at a time, each time pivoting on the
+    largest remaining diagonal entry of C - L L^T (Harbrecht, Peters and
+    Schneider's low-rank approximation, the method the paper names), so only
+    M columns of C are ever formed.  The KL pairs are those of the low-rank
+    matrix L L^T: with L^T L = Q diag(lambda) Q^T, its eigenvectors are
+    phi = L Q lambda^-1/2, so sqrt(lambda_k) phi_k(x_i) = (L Q)_ik at the mesh
+    points.  Away from them the factor row of a point x is the one that
+    reproduces the pivot columns, L(x) = C(x, P) L_P^-T (L_P: the pivot rows
+    of L), which agrees with L at the mesh points.
+
+    points : (N, d) mesh points;  rank : M;  sig_kl : the kernel's sigma_KL
+    """
+
+    def __init__(self, points, sig_kl, rank):
+        pts = np.asarray(points, dtype=np.float64)
+        N = pts.shape[0]
+        M = int(rank)
+        if not 1 <= M <= N:
+            raise ValueError("rank must be in 1..N")
+        self.pts = pts
+        self.sig_kl = float(sig_kl)
+        L = np.zeros((N, M))
+        d = np.ones(N)  # diagonal of C (unit variance kernel)
+        piv = []
+        for m in range(M):
+            p = int(np.argmax(d))
+            piv.append(p)
+            col = gauss_kernel(pts, pts[p:p + 1], self.sig_kl)[:, 0] - L[:, :m] @ L[p, :m]
+            L[:, m] = col / np.sqrt(d[p])
+            d = d - L[:, m] ** 2
+            d[piv] = 0.0
+        self.L = L
+        self.piv = np.array(piv)
+        self.trace_error = float(N - (L * L).sum())  # trace(C - L L^T), C_ii = 1
+        lam, Q = np.linalg.eigh(L.T @ L)
+        order = np.argsort(lam)[::-1]
+        lam = lam[order]
+        Q = Q[:, order]
+        V = L @ Q
+        for k in range(M):  # sign: positive sum over the mesh points, else first significant entry
+            tot = V[:, k].sum()
+            if abs(tot) > 1e-10 * np.abs(V[:, k]).sum():
+                sgn = np.sign(tot)
+            else:
+                j = int(np.argmax(np.abs(V[:, k]) > 1e-12 * np.abs(V[:, k]).max()))
+                sgn = np.sign(V[j, k])
+            Q[:, k] *= sgn
+        self.lambdas = lam
+        self.Q = Q
+
+    def factor_rows(self, x):
+        """L(x) = C(x, P) L_P^-T, shape (p, M)."""
+        Cx = gauss_kernel(x, self.pts[self.piv], self.sig_kl)
+        LP = self.L[self.piv, :]
+        return np.linalg.solve(LP, Cx.T).T
+
+    def modes(self, x):
+        """modes[e, k] = sqrt(lambda_k) phi_k(x_e), shape (p, M)."""
+        return self.factor_rows(x) @ self.Q
+
+
+def damping(modes_on_mesh, s, delta):
+    """The factor s of the expansion, lowered where needed so that
+    s * max_x sum_k |sqrt(lambda_k) phi_k(x)| <= delta: the largest
+    perturbation over all y in [-1, 1]^M then stays within delta G_0, the
+    paper's uniform-ellipticity requirement (Sec. 2.2)."""
+    bound = np.abs(modes_on_mesh).sum(axis=1).max()
+    return min(float(s), float(delta) / bound)
+
+
+def synthesize_additive(modes, y, g0):
+    """G[s, e] = g0 * (1 + sum_k modes[e, k] y[s, k]) with the damping folded into modes."""
+    modes = np.asarray(modes, dtype=np.float64)
+    y = np.atleast_2d(np.asarray(y, dtype=np.float64))
+    return g0 * (1.0 + y @ modes.T)

@@ -72,6 +72,7 @@ class STProblem:
     sigma_f0: float = 1e-3
     transverse_ratio: float = 0.1
     fiber_law: str = "diag2d"
+    tau_relative: bool = False  # transverse conductivity transverse_ratio * sigma_e instead of * sigma_f0
     source: object = None
     newton_atol: float = 1e-12
     newton_max: int = 50
@@ -84,7 +85,11 @@ class STProblem:
 
     @property
     def tau(self):
-        return self.transverse_ratio * self.sigma_f0
+        return 0.0 if self.tau_relative else self.transverse_ratio * self.sigma_f0
+
+    @property
+    def tau_rel(self):
+        return self.transverse_ratio if self.tau_relative else 0.0
 
     def mass(self):
         if "M" not in self._cache:
@@ -93,7 +98,7 @@ class STProblem:
 
     def stiffness(self, sigma):
         theta = fem.fiber_angles(self.grid, self.fiber_law)
-        D = fem.diffusion_tensors(sigma, theta, self.tau, self.grid.dim)
+        D = fem.diffusion_tensors(sigma, theta, self.tau, self.grid.dim, self.tau_rel)
         return fem.assemble_stiffness(self.grid, D)
 
     def load(self, t, nq=3):

@@ -66,6 +66,9 @@ def problem_from_workload(wl, **overrides):
                     p.levels[i].team_seconds[g] = float(sec)
     p.n_modes = wl["n_modes"]
     p.theta = wl.get("theta", 1.0)
+    p.field_kind = _lib.FIELD_KINDS[wl.get("field", "lognormal")]
+    p.tau_relative = int(wl.get("tau_relative", 0))
+    p.ic_kind = _lib.IC_KINDS[wl.get("ic_kind", "ball")]
     prec = overrides.pop("precision", wl.get("precision", "fp64"))
     p.precision = _lib.PRECISIONS[prec]
     for k, v in overrides.items():

@@ -17,6 +17,8 @@ STATUS = {
 }
 FIBER_LAWS = {"diag2d": 0, "rot3d": 1, "x": 2, "diag": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
+FIELD_KINDS = {"lognormal": 0, "additive": 1}
+IC_KINDS = {"ball": 0, "gauss": 1}
 
 
 class StmLevel(ctypes.Structure):
@@ -54,6 +56,9 @@ class StmProblem(ctypes.Structure):
         ("max_lanes", ctypes.c_int),
         ("team_size", ctypes.c_int),
         ("theta", ctypes.c_double),
+        ("field_kind", ctypes.c_int),
+        ("tau_relative", ctypes.c_int),
+        ("ic_kind", ctypes.c_int),
     ]
 
 

@@ -12,7 +12,8 @@
 // registers while the matrix cores work on the current chunk from one of two
 // LDS buffers, so one barrier per step suffices.  The split path splits each
 // value into its fp16 halves once, when it is written to LDS.  The exponential
-// is fused into the epilogue; the float64 result is written once.
+// (1 + g for the additive field) is fused into the epilogue; the float64
+// result is written once.
 //
 // Two operand paths:
 //  * float64: v_mfma_f64_16x16x4f64, exact float64 arithmetic.
@@ -128,7 +129,7 @@ struct KlF64 {
     }
   }
   __device__ void store(double* __restrict__ sigma, int S, int E, int s0, int e0, int li, int lk,
-                        double sigma_f0) const {
+                        double sigma_f0, bool additive) const {
     const bool inside = s0 + 16 <= S && e0 + KL_TILE_E <= E;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -136,7 +137,8 @@ struct KlF64 {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = s0 + lk + 4 * r;
-        if (inside || (s < S && e < E)) sigma[(int64_t)s * E + e] = sigma_f0 * exp(acc[t][r]);
+        const double g = acc[t][r];
+        if (inside || (s < S && e < E)) sigma[(int64_t)s * E + e] = sigma_f0 * (additive ? 1.0 + g : exp(g));
       }
     }
   }
@@ -184,7 +186,7 @@ struct KlF16x3 {
     }
   }
   __device__ void store(double* __restrict__ sigma, int S, int E, int s0, int e0, int li, int lk,
-                        double sigma_f0) const {
+                        double sigma_f0, bool additive) const {
     const bool inside = s0 + 16 <= S && e0 + KL_TILE_E <= E;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -193,7 +195,8 @@ struct KlF16x3 {
       for (int r = 0; r < 4; ++r) {
         const int s = s0 + 4 * lk + r;
         const float g = acc_hh[t][r] + acc_x[t][r] * (1.0f / 2048.0f);
-        if (inside || (s < S && e < E)) sigma[(int64_t)s * E + e] = sigma_f0 * (double)expf(g);
+        if (inside || (s < S && e < E))
+          sigma[(int64_t)s * E + e] = sigma_f0 * (additive ? 1.0 + (double)g : (double)expf(g));
       }
     }
   }
@@ -205,7 +208,7 @@ template <class P>
 __global__ __launch_bounds__(KL_THREADS) void kl_kernel(const double* __restrict__ modes,
                                                         const double* __restrict__ xi,
                                                         double* __restrict__ sigma, int S, int E, int M,
-                                                        double sigma_f0, int tiles_per_block) {
+                                                        double sigma_f0, int tiles_per_block, int additive) {
   constexpr int KC = P::KC;
   __shared__ typename P::Lds L;
   const int nts = (S + KL_TILE_S - 1) / KL_TILE_S;
@@ -238,14 +241,14 @@ __global__ __launch_bounds__(KL_THREADS) void kl_kernel(const double* __restrict
     }
     p.mma(L, buf, wave, li, lk);
     if (now.k0 + KC >= M) {
-      p.store(sigma, S, E, now.sb + wave * 16, now.e0, li, lk, sigma_f0);
+      p.store(sigma, S, E, now.sb + wave * 16, now.e0, li, lk, sigma_f0, additive != 0);
       p.zero();
     }
   }
 }
 
 hipError_t launch_kl_synthesize(const double* modes, const double* xi, double* sigma, int S, int E, int M,
-                                double sigma_f0, bool split_fp16, hipStream_t st) {
+                                double sigma_f0, bool split_fp16, bool additive, hipStream_t st) {
   if (S <= 0 || E <= 0) return hipSuccess;
   // resident blocks of each variant on the current device, looked up once
   static int resident[64][2];
@@ -269,10 +272,10 @@ hipError_t launch_kl_synthesize(const double* modes, const double* xi, double* s
   const int blocks = (int)((ntiles + per_block - 1) / per_block);
   if (split_fp16)
     hipLaunchKernelGGL(kl_kernel<KlF16x3>, dim3(blocks), dim3(KL_THREADS), 0, st, modes, xi, sigma, S, E, M,
-                       sigma_f0, per_block);
+                       sigma_f0, per_block, additive ? 1 : 0);
   else
     hipLaunchKernelGGL(kl_kernel<KlF64>, dim3(blocks), dim3(KL_THREADS), 0, st, modes, xi, sigma, S, E, M,
-                       sigma_f0, per_block);
+                       sigma_f0, per_block, additive ? 1 : 0);
   return hipGetLastError();
 }
 

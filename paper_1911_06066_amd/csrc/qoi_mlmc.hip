@@ -15,19 +15,14 @@
 
 namespace stm {
 
-__global__ void activation_kernel(GridDev g, int dim, int m, double dt, double T, double thr, double cx, double cy,
-                                  double cz, double r2, const double* __restrict__ u, int S,
+__global__ void activation_kernel(GridDev g, int m, double dt, double T, double thr,
+                                  const double* __restrict__ u0, const double* __restrict__ u, int S,
                                   double* __restrict__ t_act, int* __restrict__ censored) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   int cen = 0;
   if (i < g.n) {
-    const int ix = i % g.nx;
-    const int r = i / g.nx;
-    const int iy = (dim == 2) ? r : r % g.ny;
-    const int iz = (dim == 2) ? 0 : r / g.ny;
-    const double x = ix * g.hx - cx, y = iy * g.hy - cy, z = (dim == 3) ? iz * g.hz - cz : 0.0;
-    double prev = (x * x + y * y + z * z <= r2) ? 1.0 : 0.0;
+    double prev = u0[i];
     double t = -1.0;
     if (prev >= thr) {
       t = 0.0;
@@ -59,12 +54,11 @@ __global__ void activation_kernel(GridDev g, int dim, int m, double dt, double T
   if (threadIdx.x == 0 && censored && sc[0]) atomicAdd(censored + s, sc[0]);
 }
 
-hipError_t launch_activation_map(const GridDev& g, int dim, int m, double dt, double T, double thr, double cx,
-                                 double cy, double cz, double r2, const double* u, int S, double* t_act,
-                                 int* censored_dev, hipStream_t st) {
+hipError_t launch_activation_map(const GridDev& g, int m, double dt, double T, double thr, const double* u0,
+                                 const double* u, int S, double* t_act, int* censored_dev, hipStream_t st) {
   if (S <= 0) return hipSuccess;
   dim3 grid((g.n + 255) / 256, S);
-  hipLaunchKernelGGL(activation_kernel, grid, dim3(256), 0, st, g, dim, m, dt, T, thr, cx, cy, cz, r2, u, S, t_act,
+  hipLaunchKernelGGL(activation_kernel, grid, dim3(256), 0, st, g, m, dt, T, thr, u0, u, S, t_act,
                      censored_dev);
   return hipGetLastError();
 }

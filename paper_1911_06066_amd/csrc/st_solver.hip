@@ -84,15 +84,16 @@ struct TensorOf<T, 2> { using type = Tensor2<T>; };
 template <typename T>
 struct TensorOf<T, 3> { using type = Tensor3<T>; };
 
-// Element tensor from the fibre conductivity s and the fibre-row table entry f.
+// Element tensor from the fibre conductivity s and the fibre-table row f
+// (kFibStride entries; the layout is described with kFibStride); zr is uniform.
 template <typename T, int DIM>
 __device__ __forceinline__ typename TensorOf<T, DIM>::type tensor_from(double s, const double* __restrict__ f,
-                                                                       double tau) {
+                                                                       double tau, double zr) {
   const double c2 = f[0], s2 = f[1], cs = f[2];
   if constexpr (DIM == 2) {
     return Tensor2<T>{T(s * c2 + tau * s2), T(s * s2 + tau * c2), T((s - tau) * cs)};
   } else {
-    return Tensor3<T>{T(s * c2 + tau * s2), T(s * s2 + tau * c2), T(tau), T((s - tau) * cs)};
+    return Tensor3<T>{T(s * c2 + tau * s2), T(s * s2 + tau * c2), T(fma(s, zr, tau)), T((s - tau) * cs)};
   }
 }
 
@@ -276,7 +277,7 @@ struct Team {
     const int nzz = (DIM == 3) ? g.nz : 1;
     const double* __restrict__ sg = sigma;
     const double* __restrict__ fib = L->fib;
-    const double tau = prm.tau;
+    const double tau = prm.tau, zr = prm.zr;
     const T hx = T(g.hx), hy = T(g.hy), hz = T(g.hz);
     const T cxx = (DIM == 3) ? hy * hz / (T(36) * hx) : hy / (T(6) * hx);
     const T cyy = (DIM == 3) ? hx * hz / (T(36) * hy) : hx / (T(6) * hy);
@@ -368,7 +369,7 @@ struct Team {
               if (q < nse) ls[q] = rs[u];
             }
           }
-          for (int q = threadIdx.x; q < 3 * nfr; q += BLOCK) lf[q] = fib[3 * fr0 + q];
+          for (int q = threadIdx.x; q < kFibStride * nfr; q += BLOCK) lf[q] = fib[kFibStride * fr0 + q];
         }
         __syncthreads();
         STM_T1P(t_st, 6);
@@ -389,7 +390,7 @@ struct Team {
             const int r = fdiv(rem, mex);
             const int ex = rem - r * EX;
             const int ey = ey0 + r, ez = ez0 + lz;
-            D[h] = tensor_from<T, DIM>(ls[qq], lf + 3 * ((DIM == 3) ? lz : r), tau);
+            D[h] = tensor_from<T, DIM>(ls[qq], lf + kFibStride * ((DIM == 3) ? lz : r), tau, zr);
             const int base = ((ez - kr0) * sy + (ey - jr0)) * nx + ex;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -796,6 +797,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   const int m = L->m;
   const double dt = uni(L->dt), inv_dt = uni(1.0 / L->dt);
   const double kr = uni(prm.k_react), ar = uni(prm.a_react), tau = uni(prm.tau), thr = uni(prm.threshold);
+  const double zr = uni(prm.zr);
   const double th = uni(prm.theta);
   const int restart = prm.restart;
 
@@ -835,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
               const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * Gz + c;
               const int fe = (DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx);
               if (l == 1) {
-                auto D = tensor_from<double, DIM>(tm.sigma[fe], L->fib + 3 * ((DIM == 3) ? fz : fy), tau);
+                auto D = tensor_from<double, DIM>(tm.sigma[fe], L->fib + kFibStride * ((DIM == 3) ? fz : fy), tau, zr);
                 a0 += D.xx;
                 a1 += D.yy;
                 a3 += D.xy;
@@ -857,7 +859,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     }
     // diagonal of the stiffness matrix on grid 0 (sigma is fixed for the sample),
     // initial state, activation markers, warm-start history
-    tm.bytes = uni(tm.bytes + ((16.0 + sizeof(TI) + 24.0) * n0));
+    tm.bytes = uni(tm.bytes + ((24.0 + sizeof(TI) + 24.0) * n0));
     for (int q = tid; q < nb; q += BLOCK) {
       const int idx = tm.bidx(q);
       int i, j, k;
@@ -868,12 +870,11 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           g0, i, j, k, z, z,
           [&](int ex, int ey, int ez) {
             const int e = (DIM == 3) ? ((ez * g0.ey + ey) * g0.ex + ex) : (ey * g0.ex + ex);
-            return tensor_from<double, DIM>(tm.sigma[e], L->fib + 3 * ((DIM == 3) ? ez : ey), tau);
+            return tensor_from<double, DIM>(tm.sigma[e], L->fib + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
           },
           0.0, &dd);
       tm.kdiag0[idx] = dd;
-      const double x = i * g0.hx - L->ic_cx, y = j * g0.hy - L->ic_cy, zc = (DIM == 3) ? (k * g0.hz - L->ic_cz) : 0.0;
-      const double v = (x * x + y * y + zc * zc <= L->ic_r2) ? 1.0 : 0.0;
+      const double v = L->u0[idx];
       uprev[idx] = v;
       wk1[idx] = v;
       tact[idx] = (v >= thr) ? 0.0 : -1.0;

@@ -22,6 +22,7 @@ struct LevelHost {
   int64_t team_bytes;    // workspace per team without the space-time buffer
   int64_t u_bytes;       // space-time buffer m * n0 float64
   double* fib = nullptr; // device fibre table
+  double* u0 = nullptr;  // device initial state at the nodes of grid 0
 };
 
 }  // namespace
@@ -144,6 +145,12 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
     return fail(c, STM_E_UNSUPPORTED,
                 "mg_levels other than 1 is disabled: the multi-grid V-cycle kernel faulted once on the GPU "
                 "with no cause found yet; the single-grid preconditioner is the supported path");
+  if (p.field_kind != STM_FIELD_LOGNORMAL && p.field_kind != STM_FIELD_ADDITIVE)
+    return fail(c, STM_E_INVALID, "field_kind must be 0 (lognormal) or 1 (additive)");
+  if (p.tau_relative != 0 && p.tau_relative != 1) return fail(c, STM_E_INVALID, "tau_relative must be 0 or 1");
+  if (p.ic_kind != STM_IC_BALL && p.ic_kind != STM_IC_GAUSS) return fail(c, STM_E_INVALID, "ic_kind must be 0 or 1");
+  if (p.ic_kind == STM_IC_GAUSS && !(p.ic_radius > 0))
+    return fail(c, STM_E_INVALID, "the Gaussian initial state needs ic_radius > 0");
   if (!(p.theta == 0 || (p.theta >= 0.5 && p.theta <= 1.0)))
     return fail(c, STM_E_INVALID, "theta must be 0 (default) or in [1/2, 1]");
   if (p.lds_kb < 0 || p.lds_kb > 160) return fail(c, STM_E_INVALID, "lds_kb must be in 0..160");
@@ -220,25 +227,48 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   d.nmg = nmg;
   d.sweeps = lv.smooth_sweeps > 0 ? lv.smooth_sweeps : p.coarse_sweeps;
   d.cheb_ratio = lv.cheb_ratio > 0 ? lv.cheb_ratio : p.cheb_ratio;
-  d.ic_cx = p.ic_center[0];
-  d.ic_cy = p.ic_center[1];
-  d.ic_cz = p.dim == 3 ? p.ic_center[2] : 0.0;
-  d.ic_r2 = p.ic_radius * p.ic_radius;
+
   // fibre table per element row (2D) / layer (3D)
   const GridDev& g0 = d.g[0];
   const int rows = p.dim == 2 ? g0.ey : g0.ez;
-  std::vector<double> fib(3 * rows);
+  std::vector<double> fib(kFibStride * rows);
+  const double ratio = p.transverse_ratio;
   for (int r = 0; r < rows; ++r) {
     const double yc = (r + 0.5) * g0.hy, zc = (r + 0.5) * g0.hz;
     const double th = p.dim == 2 ? fiber_angle(p, yc, 0.0) : fiber_angle(p, 0.0, zc);
     const double cth = std::cos(th), sth = std::sin(th);
-    fib[3 * r] = cth * cth;
-    fib[3 * r + 1] = sth * sth;
-    fib[3 * r + 2] = cth * sth;
+    double* f = fib.data() + kFibStride * r;
+    if (p.tau_relative) {  // tau_e = ratio sigma_e
+      f[0] = cth * cth + ratio * sth * sth;
+      f[1] = sth * sth + ratio * cth * cth;
+      f[2] = (1.0 - ratio) * cth * sth;
+    } else {  // tau = ratio sigma_f0
+      f[0] = cth * cth;
+      f[1] = sth * sth;
+      f[2] = cth * sth;
+    }
   }
   STM_HIP(c, hipMalloc(&out.fib, fib.size() * sizeof(double)));
   STM_HIP(c, hipMemcpy(out.fib, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice));
   d.fib = out.fib;
+  {
+    // initial state at the nodes of grid 0: the ball or the Gaussian bump
+    const GridDev& g = d.g[0];
+    const double cx = p.ic_center[0], cy = p.ic_center[1], cz = p.dim == 3 ? p.ic_center[2] : 0.0;
+    const double r2 = p.ic_radius * p.ic_radius;
+    std::vector<double> u0((size_t)g.n);
+    for (int k = 0; k < g.nz; ++k)
+      for (int j = 0; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) {
+          const double x = i * g.hx - cx, y = j * g.hy - cy, z = p.dim == 3 ? k * g.hz - cz : 0.0;
+          const double d2 = x * x + y * y + z * z;
+          u0[((size_t)k * g.ny + j) * g.nx + i] =
+              p.ic_kind == STM_IC_GAUSS ? std::exp(-d2 / r2) : (d2 <= r2 ? 1.0 : 0.0);
+        }
+    STM_HIP(c, hipMalloc(&out.u0, u0.size() * sizeof(double)));
+    STM_HIP(c, hipMemcpy(out.u0, u0.data(), u0.size() * sizeof(double), hipMemcpyHostToDevice));
+    d.u0 = out.u0;
+  }
   // team workspace layout
   const size_t ti = c->inner_fp32 ? 4 : 8;
   const int n0 = g0.n;
@@ -281,7 +311,7 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
         // four staged nodal fields, element conductivities, element
         // contributions, fibre rows of the tile
         const size_t bytes = 4 * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex + 16 +
-                             24 * (size_t)(p.dim == 2 ? ey : ez);
+                             8 * kFibStride * (size_t)(p.dim == 2 ? ey : ez);
         if (bytes > budget) break;
         const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
         if (eff > best) {
@@ -484,7 +514,8 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
   SolverParams& s = c->prm;
   s.k_react = c->p.k_react;
   s.a_react = c->p.a_react;
-  s.tau = c->p.transverse_ratio * c->p.sigma_f0;
+  s.tau = c->p.tau_relative ? 0.0 : c->p.transverse_ratio * c->p.sigma_f0;
+  s.zr = c->p.tau_relative ? c->p.transverse_ratio : 0.0;
   s.threshold = c->p.threshold;
   s.newton_tol = c->p.newton_tol;
   s.gmres_rtol = c->p.gmres_rtol;
@@ -504,8 +535,10 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
 void stm_destroy(stm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  for (auto& l : c->levels)
+  for (auto& l : c->levels) {
     if (l.fib) (void)hipFree(l.fib);
+    if (l.u0) (void)hipFree(l.u0);
+  }
   if (c->d_levels) (void)hipFree(c->d_levels);
   if (c->work) (void)hipFree(c->work);
   if (c->d_tasks) (void)hipFree(c->d_tasks);
@@ -548,7 +581,8 @@ stm_status stm_kl_synthesize(stm_ctx* c, int level, const double* modes, const d
   reset_timings(c);
   if ((st = timed_begin(c))) return st;
   hipError_t e = launch_kl_synthesize(modes, xi, sigma, S, E, c->p.n_modes, c->p.sigma_f0,
-                                      c->p.precision == STM_PREC_MIXED, c->stream);
+                                      c->p.precision == STM_PREC_MIXED, c->p.field_kind == STM_FIELD_ADDITIVE,
+                                      c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "kl launch");
   return timed_end(c, &c->tm.kl_ms);
 }
@@ -630,8 +664,7 @@ stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, dou
   }
   reset_timings(c);
   if ((st = timed_begin(c))) return st;
-  hipError_t e = launch_activation_map(d.g[0], d.dim, d.m, d.dt, d.T, c->p.threshold, d.ic_cx, d.ic_cy, d.ic_cz,
-                                       d.ic_r2, u, S, t_act, cen, c->stream);
+  hipError_t e = launch_activation_map(d.g[0], d.m, d.dt, d.T, c->p.threshold, d.u0, u, S, t_act, cen, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "activation launch");
   if ((st = timed_end(c, &c->tm.stats_ms))) return st;
   if (n_censored_host) {
@@ -816,6 +849,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
   int rounds = 0;
   int worst = 0;
   const bool mixed = c->p.precision == STM_PREC_MIXED;
+  const bool additive = c->p.field_kind == STM_FIELD_ADDITIVE;
   const int lane_budget = c->p.max_lanes;
 
   reset_timings(c);
@@ -828,12 +862,12 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       if (n1 <= n0) continue;
       const int ef = c->levels[l].dev.g[0].ne;
       hipError_t e = launch_kl_synthesize(modes_host[l], xi_host[l] + (size_t)n0 * M, S0 + off_sf[l] + (size_t)n0 * ef,
-                                          n1 - n0, ef, M, c->p.sigma_f0, mixed, c->stream);
+                                          n1 - n0, ef, M, c->p.sigma_f0, mixed, additive, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "kl launch");
       if (l > 0) {
         const int ec = c->levels[l - 1].dev.g[0].ne;
         e = launch_kl_synthesize(modes_host[l - 1], xi_host[l] + (size_t)n0 * M, S0 + off_sc[l] + (size_t)n0 * ec,
-                                 n1 - n0, ec, M, c->p.sigma_f0, mixed, c->stream);
+                                 n1 - n0, ec, M, c->p.sigma_f0, mixed, additive, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "kl launch");
       }
     }

@@ -43,7 +43,7 @@ struct LevelDev {
   double cheb_ratio;            // Chebyshev interval ratio of the sweep weights
   GridDev g[kMaxMG];
   const double* fib;            // grid-0 fibre table: per element row (2D) / layer (3D): c^2, s^2, c s
-  double ic_cx, ic_cy, ic_cz, ic_r2;
+  const double* u0;     // initial state at the nodes of grid 0 (filled by the host)
   // team workspace layout (bytes from the team base)
   int64_t off_u, off_uprev, off_wk1, off_tact;          // float64 [n0]
   int64_t off_V, off_Z;                                 // inner [restart+1][n0], [restart][n0]
@@ -61,7 +61,8 @@ struct LevelDev {
 // Physics and solver parameters (uniform across a launch).
 struct SolverParams {
   double k_react, a_react;
-  double tau;           // transverse conductivity
+  double tau;           // constant part of the transverse conductivity (0 when it is relative)
+  double zr;            // D_zz = tau + zr sigma_e (3D)
   double threshold;
   double newton_tol;
   double gmres_rtol;
@@ -77,6 +78,14 @@ struct SolverParams {
 };
 
 constexpr int kMaxSweeps = 32;
+
+// Fibre table: per element row (2D) or layer (3D) the entries (c2, s2, cs) of
+// D_e = (sigma_e c2 + tau s2, sigma_e s2 + tau c2, (sigma_e - tau) cs) in the
+// x-y plane; D_zz = tau + zr sigma_e.  The fibre model takes
+// (cos^2, sin^2, cos sin), tau = ratio sigma_f0 and zr = 0; a transverse
+// conductivity ratio sigma_e takes (cos^2 + ratio sin^2, sin^2 + ratio cos^2,
+// (1 - ratio) cos sin), tau = 0 and zr = ratio, which with ratio 1 is sigma_e I.
+constexpr int kFibStride = 3;
 
 // A team of G workgroups solves `count` samples s = first + i * stride in
 // order.  One TeamTask per workgroup: the members of a team carry identical

@@ -20,13 +20,13 @@ int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t l
 
 // sigma[s][e] = sigma_f0 * exp(sum_k modes[e][k] xi[s][k]) on the matrix cores.
 // split_fp16: operands split into fp16 hi/lo pairs, fp32 accumulation; else float64 MFMA.
+// sigma = sigma_f0 exp(g) (lognormal) or sigma_f0 (1 + g) (additive), g = xi modes^T.
 hipError_t launch_kl_synthesize(const double* modes, const double* xi, double* sigma, int S, int E, int M,
-                                double sigma_f0, bool split_fp16, hipStream_t st);
+                                double sigma_f0, bool split_fp16, bool additive, hipStream_t st);
 
-// Activation map of u[S][m][n] with initial state given by the ball (cx, cy, cz, r2) on grid g.
-hipError_t launch_activation_map(const GridDev& g, int dim, int m, double dt, double T, double thr, double cx,
-                                 double cy, double cz, double r2, const double* u, int S, double* t_act,
-                                 int* censored_dev, hipStream_t st);
+// Activation map of u[S][m][n] on grid g, with initial state u0[n] (device).
+hipError_t launch_activation_map(const GridDev& g, int m, double dt, double T, double thr, const double* u0,
+                                 const double* u, int S, double* t_act, int* censored_dev, hipStream_t st);
 
 // MLMC statistics of one level on the finest grid.
 struct StatsLevelArgs {

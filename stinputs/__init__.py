@@ -17,6 +17,9 @@ grid whose element counts are 64 x 64 x 16 etc.):
                 (ell 0.15, s2 0.2), 256 samples, mixed precision
   mlmc5_3d      five 3D levels 9x9x3 ... 129x129x33 nodes, 32 ... 512 steps,
                 128 modes, sample counts chosen adaptively
+  cube4_3d      the paper's cube: [0,1]^3 cm, 6^3 ... 41^3 nodes, 24 ... 192
+                steps to 0.96 ms, isotropic additive uniform field (Gaussian
+                kernel, 66 modes), 1024/256/64/16 pairs, FP64
 """
 
 import numpy as np
@@ -60,6 +63,39 @@ _COMMON_3D = dict(
 )
 
 
+# The paper's cube experiment (Sec. 4, "Parameters for the experiments",
+# "Parameters for KL expansion", Table 2).  Lengths in cm, times in ms, the
+# potential in units of u_peak = 115 mV: the FHN current
+# alpha (u - 0)(u - 28)(u - 115) becomes k v (v - a)(1 - v) with
+# k = alpha u_peak^2 and a = u_th / u_peak.  Isotropic conductivity
+# G = G_0 (1 + s sum_k sqrt(lambda_k) phi_k(x) y_k), y_k ~ U(-1, 1), Gaussian
+# kernel exp(-d^2 / sigma_KL); the Gaussian stimulus of width 0.5 cm is the
+# initial state; Crank-Nicolson as in the paper.
+_ALPHA, _U_TH, _U_PEAK = 1.4e-3, 28.0, 115.0
+_CUBE_3D = dict(
+    dim=3,
+    lengths=(1.0, 1.0, 1.0),
+    T=0.96,
+    k_react=_ALPHA * _U_PEAK * _U_PEAK,
+    a_react=_U_TH / _U_PEAK,
+    sigma_f0=3.325e-3,
+    transverse_ratio=1.0,
+    tau_relative=1,
+    fiber_law="x",
+    ic_kind="gauss",
+    ic_center=(0.0, 0.0, 0.0),
+    ic_radius=0.5,
+    threshold=0.5,
+    theta=0.5,
+    field="additive",
+    kernel="gauss",
+    sig_kl=0.25,
+    kl_s=0.3,
+    kl_delta=0.5,
+    xi_dist="uniform",
+)
+
+
 def _w(base, **kw):
     d = dict(base)
     d.update(kw)
@@ -82,6 +118,10 @@ WORKLOADS = {
                    levels=[(9, 9, 3), (17, 17, 5), (33, 33, 9), (65, 65, 17), (129, 129, 33)],
                    steps=[32, 64, 128, 256, 512], n_modes=128, samples=None,
                    target_rmse=1e-3, pilot=32, precision="mixed"),
+    "cube4_3d": _w(_CUBE_3D, name="cube4_3d",
+                   levels=[(6, 6, 6), (11, 11, 11), (21, 21, 21), (41, 41, 41)],
+                   steps=[24, 48, 96, 192], n_modes=66, kl_grid=(41, 41, 41),
+                   samples=[1024, 256, 64, 16], precision="fp64"),
 }
 
 WORKLOAD_IDS = {name: i for i, name in enumerate(WORKLOADS)}
@@ -95,14 +135,18 @@ def workload(name, **overrides):
 
 
 def xi(name, level, n_samples, n_modes, seed=DEFAULT_SEED, start=0):
-    """Standard normal KL coefficients (n_samples, n_modes) for one MLMC level.
+    """KL coefficients (n_samples, n_modes) for one MLMC level: standard normal,
+    or uniform on [-1, 1] for workloads whose xi_dist is 'uniform'.
 
     One PCG64 stream per (seed, workload, level), drawn in sample order, so a
     longer draw extends a shorter one (prefix stable): rows start .. start+n.
     """
     ss = np.random.SeedSequence([seed, WORKLOAD_IDS.get(name, 99), level])
     g = np.random.Generator(np.random.PCG64(ss))
-    full = g.standard_normal((start + n_samples, n_modes))
+    if WORKLOADS.get(name, {}).get("xi_dist", "normal") == "uniform":
+        full = g.uniform(-1.0, 1.0, size=(start + n_samples, n_modes))
+    else:
+        full = g.standard_normal((start + n_samples, n_modes))
     return np.ascontiguousarray(full[start:])
 
 
