@@ -106,6 +106,48 @@ def cpu_baseline(wl, modes, N, total_dof_steps, budget_s):
     }
 
 
+def warm_starts(wl, modes, xi, k=4):
+    """First Newton iterates on the finest level, one workgroup per sample:
+    the previous sample's solution (one lane solving k samples in turn), the
+    space-time prolongation of the pair's coarse solution (Sec. 3.4), and the
+    initial state (cold).  Per-sample Newton and Krylov iterations and device
+    seconds (the coarse solve and the prolongation are reported apart)."""
+    import torch
+
+    from paper_1911_06066_amd import Context
+
+    L = len(wl["levels"]) - 1
+    y = xi[L][:k + 1].contiguous()
+    out = {"samples": k, "level": L}
+
+    def summary(st):
+        return {"newton_per_sample": sum(s["newton_iters"] for s in st) / len(st),
+                "krylov_per_sample": sum(s["krylov_iters"] for s in st) / len(st),
+                "seconds_per_sample": sum(s["device_seconds"] for s in st) / len(st)}
+
+    from paper_1911_06066_amd import autotune
+    tun = autotune.level_tuning(wl, wl["precision"])
+    over = {"level_tuning": tun} if tun else {}
+    one = Context(wl, max_lanes=1, team_size=1, **over)
+    many = Context(wl, max_lanes=k, team_size=1, **over)
+    sf_all = many.kl_synthesize(L, modes[L], y)
+    _, st = one.st_solve(L, sf_all)
+    out["previous_sample"] = summary(st[1:])  # the lane's first sample starts cold
+    sf = sf_all[1:].contiguous()
+    sc = many.kl_synthesize(L - 1, modes[L - 1], y[1:].contiguous())
+    uc, stc = many.st_solve(L - 1, sc)
+    guess = many.prolong_st(L, uc)
+    torch.cuda.synchronize()
+    pro_ms = many.timings()["stats_ms"]
+    _, st = many.st_solve(L, sf, u0_guess=guess)
+    out["prolonged_coarse"] = summary(st)
+    out["prolonged_coarse"]["coarse_seconds_per_sample"] = summary(stc)["seconds_per_sample"]
+    out["prolonged_coarse"]["prolongation_ms"] = pro_ms
+    _, st = many.st_solve(L, sf)
+    out["initial_state"] = summary(st)
+    return out
+
+
 def compare_paths(wl, N, modes, xi, fp64_value, fp64_out):
     """The same MLMC estimate (same samples, so the same RMSE) through
 
@@ -170,6 +212,7 @@ def compare_paths(wl, N, modes, xi, fp64_value, fp64_out):
     single_value = float(sum(N)) / total
     out["fp64_single_sample"] = {"value": single_value, "seconds_per_pair": per,
                                  "sample": "%d pairs per level, one st_solve call per sample, scaled to N" % k}
+    out["warm_start_finest"] = warm_starts(wl, modes, xi)
     out["mixed_batched_over_fp64_single"] = mixed_value / single_value
     out["fp64_batched_over_fp64_single"] = fp64_value / single_value
     out["mixed_batched_over_fp64_batched"] = mixed_value / fp64_value

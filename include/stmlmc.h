@@ -254,6 +254,21 @@ stm_status stm_activation_map(stm_ctx* ctx, int level, const double* u, int S, d
                               int* n_censored_host);
 
 /*
+ * Space-time prolongation P_t (x) P_h from level-1 to `level` (Sec. 3.4, the
+ * tensor-product transfer P_l = P_{l,t} (x) P_{l,h} between space-time
+ * levels), for a coarse solution to serve as the fine solve's first iterate
+ * (stm_st_solve's u0_guess).  In space: Q1 interpolation of the nested coarse
+ * grid at the fine nodes.  In time: fine level k at t = k dt_l lies at
+ * j + w = k m_{l-1} / m_l coarse steps; the value is (1 - w) U_j + w U_{j+1}
+ * of the space-interpolated coarse levels, with U_0 the fine grid's initial
+ * state (the coarse initial state is not an unknown).
+ *   u_coarse[S][m_{l-1}][n_{l-1}], u_fine[S][m_l][n_l], device, caller-owned;
+ *   1 <= level < n_levels, S >= 0 (S = 0 is a no-op).  Asynchronous on the
+ *   context stream.
+ */
+stm_status stm_prolong_st(stm_ctx* ctx, int level, const double* u_coarse, int S, double* u_fine);
+
+/*
  * MLMC estimate of the mean and variance of the activation map on the
  * finest level (Sec. 3.1.2, eq. MLMC-estimator; single level = plain MC).
  *   modes_host[l] : device pointer to modes of level l, [E_l][M]

@@ -99,6 +99,36 @@ def activation_map(wl, level, U):
     return t, cens
 
 
+def prolong_st(wl, level, U_coarse):
+    """Space-time prolongation P_t (x) P_h of level-1 solutions to `level`
+    (Sec. 3.4: tensor product of the spatial and the temporal transfer).
+
+    Space: Q1 interpolation of the nested coarse grid at the fine nodes.  Time:
+    the fine level at t = k dt_l is the linear interpolant, at that t, of the
+    coarse levels at j dt_{l-1} and (j + 1) dt_{l-1} that bracket it; the
+    coarse level at t = 0 is the fine grid's initial state.
+    """
+    gc, gf = level_grid(wl, level - 1), level_grid(wl, level)
+    mc, mf = wl["steps"][level - 1], wl["steps"][level]
+    T = wl["T"]
+    U_coarse = np.atleast_3d(U_coarse)
+    u0 = initial_state(wl, gf)
+    out = np.empty((U_coarse.shape[0], mf, gf.n))
+    for s in range(U_coarse.shape[0]):
+        levels = [u0] + [mlmc.interpolate(gc, U_coarse[s, j], gf) for j in range(mc)]
+        tc = np.arange(mc + 1) * (T / mc)
+        for k in range(1, mf + 1):
+            t = k * (T / mf)
+            j = min(int(np.searchsorted(tc, t, side="right")) - 1, mc - 1)
+            w = (t - tc[j]) / (tc[j + 1] - tc[j])
+            if abs(w - 1.0) < 1e-12:  # t on the coarse level j + 1
+                j, w = j + 1, 0.0
+            if abs(w) < 1e-12:
+                w = 0.0
+            out[s, k - 1] = levels[j] if w == 0.0 else (1.0 - w) * levels[j] + w * levels[j + 1]
+    return out
+
+
 def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
     """MLMC mean/variance of the activation map on the finest grid.
 

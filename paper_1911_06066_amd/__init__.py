@@ -183,6 +183,19 @@ class Context:
         self._raise(self.lib.stm_activation_map(self.h, level, _ptr(u), S, _ptr(out), cen))
         return out, list(cen[:S])
 
+    def prolong_st(self, level, u_coarse, out=None):
+        """Space-time prolongation of level-1 solutions (S, m_{l-1}, n_{l-1}) to level."""
+        torch = _torch()
+        nc, _, mc = self.sizes[level - 1]
+        nf, _, mf = self.sizes[level]
+        S = u_coarse.shape[0]
+        _check_dev(u_coarse, "u_coarse", torch.float64, (S, mc, nc))
+        if out is None:
+            out = torch.empty((S, mf, nf), dtype=torch.float64, device=u_coarse.device)
+        _check_dev(out, "u_fine", torch.float64, (S, mf, nf))
+        self._raise(self.lib.stm_prolong_st(self.h, level, _ptr(u_coarse), S, _ptr(out)))
+        return out
+
     def mlmc_estimate(self, N, modes, xi, capacity=None, target_rmse=0.0, pilot=0, level_fields=True):
         """N: samples per level (None = adaptive).  modes[l]: (E_l, M); xi[l]: (cap_l, M)."""
         torch = _torch()

@@ -109,6 +109,7 @@ SIGNATURES = {
                                     ctypes.POINTER(StmSolveStats)]),
     "stm_activation_map": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P,
                                           ctypes.POINTER(ctypes.c_int)]),
+    "stm_prolong_st": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P]),
     "stm_mlmc_estimate": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P),
                                          ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int),
                                          ctypes.c_double, ctypes.c_int,

@@ -115,6 +115,32 @@ __device__ __forceinline__ double interp_nested(const GridDev& gc, const GridDev
   return acc;
 }
 
+// Space-time prolongation (Sec. 3.4): fine time level k + 1 (t = (k + 1) dt_f)
+// sits at j + w = (k + 1) mc / mf coarse steps; blend the space-interpolated
+// coarse levels j and j + 1, coarse level 0 being the fine initial state.
+__global__ void prolong_st_kernel(GridDev gc, GridDev gf, int dim, int mc, int mf, const double* __restrict__ u0f,
+                                  const double* __restrict__ u_c, double* __restrict__ u_f) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;  // fine time level k + 1
+  const int s = blockIdx.z;
+  if (p >= gf.n) return;
+  const int64_t num = (int64_t)(k + 1) * mc;
+  const int j = (int)(num / mf);
+  const double w = double(num % mf) / mf;
+  const double* uc = u_c + (int64_t)s * mc * gc.n;
+  const double a = (j == 0) ? u0f[p] : interp_nested(gc, gf, dim, uc + (int64_t)(j - 1) * gc.n, p);
+  const double b = (w > 0.0) ? interp_nested(gc, gf, dim, uc + (int64_t)j * gc.n, p) : 0.0;
+  u_f[((int64_t)s * mf + k) * gf.n + p] = (1.0 - w) * a + w * b;
+}
+
+hipError_t launch_prolong_st(const GridDev& gc, const GridDev& gf, int dim, int mc, int mf, const double* u0f,
+                             const double* u_c, int S, double* u_f, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prolong_st_kernel, dim3((gf.n + 255) / 256, mf, S), dim3(256), 0, st, gc, gf, dim, mc, mf, u0f,
+                     u_c, u_f);
+  return hipGetLastError();
+}
+
 // Pass 1: Welford over each chunk of samples. part[c][0..5][p]: mean_f, M2_f, mean_c, M2_c, mean_y, M2_y.
 __global__ void level_chunk_kernel(StatsLevelArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;

@@ -675,6 +675,25 @@ stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, dou
   return STM_OK;
 }
 
+stm_status stm_prolong_st(stm_ctx* c, int level, const double* u_coarse, int S, double* u_fine) {
+  if (!c) return STM_E_INVALID;
+  c->err.clear();
+  if (level < 1 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level must be in 1 .. n_levels - 1");
+  if (S < 0) return fail(c, STM_E_INVALID, "S < 0");
+  if (S > 65535) return fail(c, STM_E_INVALID, "S > 65535 samples per call");
+  if (S == 0) return STM_OK;
+  stm_status st;
+  if ((st = check_ptr(c, u_coarse, "u_coarse")) || (st = check_ptr(c, u_fine, "u_fine"))) return st;
+  const LevelDev& dc = c->levels[level - 1].dev;
+  const LevelDev& df = c->levels[level].dev;
+  if (df.m > 65535) return fail(c, STM_E_UNSUPPORTED, "more than 65535 time steps");
+  reset_timings(c);
+  if ((st = timed_begin(c))) return st;
+  hipError_t e = launch_prolong_st(dc.g[0], df.g[0], c->p.dim, dc.m, df.m, df.u0, u_coarse, S, u_fine, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "prolongation launch");
+  return timed_end(c, &c->tm.stats_ms);
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,11 @@ int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t l
 hipError_t launch_kl_synthesize(const double* modes, const double* xi, double* sigma, int S, int E, int M,
                                 double sigma_f0, bool split_fp16, bool additive, hipStream_t st);
 
+// Space-time prolongation of S coarse solutions u_c[S][mc][gc.n] to u_f[S][mf][gf.n]:
+// nested Q1 interpolation in space, linear in time, u0f[gf.n] the fine initial state.
+hipError_t launch_prolong_st(const GridDev& gc, const GridDev& gf, int dim, int mc, int mf, const double* u0f,
+                             const double* u_c, int S, double* u_f, hipStream_t st);
+
 // Activation map of u[S][m][n] on grid g, with initial state u0[n] (device).
 hipError_t launch_activation_map(const GridDev& g, int m, double dt, double T, double thr, const double* u0,
                                  const double* u, int S, double* t_act, int* censored_dev, hipStream_t st);

@@ -1,0 +1,69 @@
+"""GPU parity of the space-time prolongation (Sec. 3.4) and its use as the
+first Newton iterate of the fine member of a pair."""
+
+import numpy as np
+import pytest
+
+import oracle.api as oapi
+import stinputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_ratio3", "3d", "cube"])
+def test_prolongation_matches_oracle(torch_dev, case):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    if case == "2d":
+        wl = stinputs.workload("small_mc_2d", levels=[(9, 7), (17, 13), (33, 25)], steps=[5, 10, 20],
+                               lengths=(1.0, 0.75))
+    elif case == "2d_ratio3":
+        wl = stinputs.workload("small_mc_2d", levels=[(9, 9), (17, 17)], steps=[4, 12])
+    elif case == "3d":
+        wl = stinputs.workload("slab3d", levels=[(9, 9, 3), (17, 17, 5)], steps=[6, 12], precision="fp64")
+    else:
+        wl = stinputs.workload("cube4_3d", levels=[(6, 6, 6), (11, 11, 11)], steps=[24, 48])
+    ctx = Context(wl)
+    L = len(wl["levels"])
+    rng = np.random.default_rng(7)
+    for l in range(1, L):
+        nc, _, mc = ctx.sizes[l - 1]
+        Uc = rng.uniform(-0.2, 1.2, (3, mc, nc))
+        Uf = ctx.prolong_st(l, torch.from_numpy(Uc).to(dev)).cpu().numpy()
+        ref = oapi.prolong_st(wl, l, Uc)
+        assert np.abs(Uf - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("workload", ["mlmc3_2d", "cube4_3d"])
+def test_prolonged_coarse_solution_as_first_iterate(torch_dev, workload):
+    """The fine solve from the prolonged coarse solution reaches the same
+    solution as from its default first iterate."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    if workload == "mlmc3_2d":
+        wl = stinputs.workload("mlmc3_2d", levels=[(17, 17), (33, 33)], steps=[16, 32], kl_grid=(17, 17))
+    else:
+        wl = stinputs.workload("cube4_3d", levels=[(6, 6, 6), (11, 11, 11)], steps=[24, 48], kl_grid=(11, 11, 11))
+    basis = oapi.kl_basis(wl)
+    modes = [torch.from_numpy(oapi.kl_modes(wl, l, basis)).to(dev) for l in range(2)]
+    y = torch.from_numpy(stinputs.xi(wl["name"], 1, 3, wl["n_modes"])).to(dev)
+    ctx = Context(wl, max_lanes=3)
+    sc = ctx.kl_synthesize(0, modes[0], y)
+    sf = ctx.kl_synthesize(1, modes[1], y)
+    uc, _ = ctx.st_solve(0, sc)
+    guess = ctx.prolong_st(1, uc)
+    u1, st1 = ctx.st_solve(1, sf)
+    u2, st2 = ctx.st_solve(1, sf, u0_guess=guess)
+    assert all(s["status"] == 0 for s in st1 + st2)
+    assert _rel(u2.cpu().numpy(), u1.cpu().numpy()) < 1e-9

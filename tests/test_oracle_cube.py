@@ -237,3 +237,46 @@ def test_product_exponential_modes_match_oracle():
     mp = klmodes.workload_modes(wl)[0]
     mo = api.kl_modes(wl, 0)
     np.testing.assert_allclose(mp @ mp.T, mo @ mo.T, rtol=0, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Space-time prolongation (Sec. 3.4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_space_time_prolongation_is_exact_on_multilinear_fields(dim):
+    """P_t (x) P_h reproduces fields that are multilinear in space and linear
+    in time (the interpolants of such fields are exact); its t = 0 end is the
+    fine initial state, which the test sets to the same field."""
+    if dim == 2:
+        wl = stinputs.workload("small_mc_2d", levels=[(5, 4), (9, 7)], steps=[3, 6], lengths=(1.0, 0.6))
+    else:
+        wl = stinputs.workload("slab3d", levels=[(3, 3, 3), (5, 5, 5)], steps=[4, 12])
+    f = lambda x, t: 0.3 + 0.7 * x[:, 0] - 1.1 * x[:, 1] + 0.4 * x[:, 0] * x[:, 1] + t * (0.5 - 0.2 * x[:, 0]) \
+        + (0.25 * x[:, -1] * x[:, 0] if dim == 3 else 0.0)
+    gc, gf = api.level_grid(wl, 0), api.level_grid(wl, 1)
+    mc, mf = wl["steps"]
+    T = wl["T"]
+    Uc = np.stack([f(gc.nodes(), (j + 1) * T / mc) for j in range(mc)])[None]
+    import oracle.api as oa
+    saved = oa.initial_state
+    oa.initial_state = lambda w, g: f(g.nodes(), 0.0)
+    try:
+        Uf = oa.prolong_st(wl, 1, Uc)
+    finally:
+        oa.initial_state = saved
+    expect = np.stack([f(gf.nodes(), (k + 1) * T / mf) for k in range(mf)])
+    np.testing.assert_allclose(Uf[0], expect, rtol=0, atol=1e-13)
+
+
+def test_space_time_prolongation_time_weights():
+    """A field constant in space: fine level k is the linear interpolant in t
+    of the coarse levels, with the initial state at t = 0 (ratio 2 and 3)."""
+    for mc, mf in ((4, 8), (2, 6)):
+        wl = stinputs.workload("small_mc_2d", levels=[(3, 3), (5, 5)], steps=[mc, mf], ic_radius=10.0)
+        Uc = np.repeat(np.arange(1, mc + 1, dtype=float)[:, None] * 2.0, 9, axis=1)[None]
+        Uf = api.prolong_st(wl, 1, Uc)[0]
+        t = np.arange(1, mf + 1) * mc / mf  # fine times in coarse steps
+        expect = np.interp(t, np.arange(mc + 1), np.concatenate([[1.0], 2.0 * np.arange(1, mc + 1)]))
+        np.testing.assert_allclose(Uf[:, 0], expect, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(Uf, Uf[:, :1].repeat(25, axis=1), rtol=0, atol=1e-14)
