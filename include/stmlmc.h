@@ -65,6 +65,13 @@ typedef enum {
 } stm_field_kind;
 
 typedef enum {
+  STM_QOI_ACTIVATION = 0,  /* the activation-time map on the finest grid, n_L values */
+  STM_QOI_SPACETIME = 1    /* the space-time solution u itself on the finest space-time grid, time levels
+                              1 .. m_L: m_L n_L values, level k at t = k dt_L (Sec. 4.1: E[u] with
+                              the error measured in L^2(0, T; L^2(D))) */
+} stm_qoi;
+
+typedef enum {
   STM_IC_BALL = 0,   /* u(x, 0) = 1 in the closed ball |x - ic_center| <= ic_radius, else 0 */
   STM_IC_GAUSS = 1   /* u(x, 0) = exp(-|x - ic_center|^2 / ic_radius^2): the paper's Gaussian
                         stimulus (Sec. 4, "Parameters for the experiments"), in units of u_peak */
@@ -72,7 +79,8 @@ typedef enum {
 
 #define STM_MAX_LEVELS 8
 
-/* One MLMC level: nodes per axis (nz = 1 in 2D, all odd) and time steps.
+/* One MLMC level: nodes per axis (nz = 1 in 2D; nx >= 3, ny >= 2 in 2D (a strip of one element
+ * row with y-constant data is the 1D problem), ny >= 3 and nz >= 2 in 3D) and time steps.
  * smooth_sweeps and cheb_ratio override the problem's coarse_sweeps and
  * cheb_ratio for this level (0 keeps the problem's value); a tuner measures
  * them per level, since the best smoother degree depends on the slab
@@ -108,7 +116,7 @@ typedef struct {
   int fiber_law;              /* stm_fiber_law */
   double ic_center[3], ic_radius;
   double threshold;
-  int n_levels;               /* 1 .. STM_MAX_LEVELS, coarse to fine, each a 2:1 refinement */
+  int n_levels;               /* 1 .. STM_MAX_LEVELS, coarse to fine, each axis refined 2:1 or kept */
   stm_level levels[STM_MAX_LEVELS];
   int n_modes;                /* KL modes M, 1 .. 256 */
   int precision;              /* stm_precision */
@@ -144,6 +152,7 @@ typedef struct {
   int field_kind;             /* stm_field_kind of stm_kl_synthesize and stm_mlmc_estimate: 0 lognormal */
   int tau_relative;           /* 0: tau_e = transverse_ratio sigma_f0; 1: tau_e = transverse_ratio sigma_e */
   int ic_kind;                /* stm_ic_kind: 0 ball */
+  int qoi;                    /* stm_qoi of stm_mlmc_estimate: 0 activation map */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */
@@ -175,13 +184,17 @@ typedef struct {
 
 /* Output of stm_mlmc_estimate. Device arrays are caller-owned, n_L = nodes of the finest level. */
 typedef struct {
-  double* mean;               /* device [n_L]: MLMC mean of the activation map */
-  double* var;                /* device [n_L]: sum_l s^2(P Q_l) - s^2(P Q_{l-1}) */
-  double* level_mean;         /* device [(L+1) n_L] or NULL: mean of Y_l = P Q_l - P Q_{l-1} */
-  double* level_var;          /* device [(L+1) n_L] or NULL: unbiased variance of Y_l */
+  /* P: the QoI's points, n_L (STM_QOI_ACTIVATION) or m_L n_L (STM_QOI_SPACETIME, row-major
+     [k][i] for time levels k = 1 .. m_L) */
+  double* mean;               /* device [P]: MLMC mean of the QoI */
+  double* var;                /* device [P]: sum_l s^2(P Q_l) - s^2(P Q_{l-1}) */
+  double* level_mean;         /* device [(L+1) P] or NULL: mean of Y_l = P Q_l - P Q_{l-1} */
+  double* level_var;          /* device [(L+1) P] or NULL: unbiased variance of Y_l */
   /* host-side outputs */
   int N[STM_MAX_LEVELS];      /* samples used per level */
-  double V[STM_MAX_LEVELS];   /* |D|^-1 int s^2(Y_l) (lumped quadrature on the finest grid) */
+  double V[STM_MAX_LEVELS];   /* |D|^-1 int s^2(Y_l) (lumped quadrature on the finest grid); for the
+                                 space-time QoI (|D| T)^-1 int int s^2(Y_l), trapezoid in time with
+                                 the deterministic t = 0 level contributing nothing */
   double cost[STM_MAX_LEVELS];/* workgroup-seconds per sample pair of the level (measured) */
   double bias_estimate;       /* |D|^-1/2 || mean(Y_L) ||_2 / (2^alpha - 1), alpha fitted (0 if L < 2) */
   int64_t newton_iters;       /* over all samples */
@@ -280,8 +293,13 @@ stm_status stm_prolong_st(stm_ctx* ctx, int level, const double* u_coarse, int S
  *                   V_l and cost per sample until the variance part of the
  *                   mean-square error is below target_rmse^2 / 2, capped by
  *                   capacity_host[l].
- * Solutions stay on the device; only activation maps are kept and reduced
- * (Welford per chunk of samples, merged in sample order).  Synchronous.
+ * With qoi = STM_QOI_ACTIVATION the solutions stay in workspace and only
+ * activation maps are kept; with STM_QOI_SPACETIME every solution is kept
+ * (capacity x m_l x n_l float64 per pair member) and its space-time
+ * prolongation to the finest space-time grid (nested Q1 in space, linear in
+ * time from the level's own initial state, Sec. 3.4) is the sample.  Either
+ * way the samples are reduced by Welford per chunk of samples, merged in
+ * sample order.  Synchronous.
  */
 stm_status stm_mlmc_estimate(stm_ctx* ctx, const int* N_host, const double* const* modes_host,
                              const double* const* xi_host, const int* capacity_host,

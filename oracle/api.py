@@ -129,8 +129,43 @@ def prolong_st(wl, level, U_coarse):
     return out
 
 
+def space_time_sample(wl, level, U, finest_level):
+    """A level's space-time solution U (m_l, n_l) on the finest space-time grid:
+    at finest time level k (t = k dt_L, k = 1 .. m_L) the linear interpolant in
+    t of the level's own time levels (level 0 its initial state), each
+    interpolated in space (nested Q1) to the finest nodes; flattened [k][i]."""
+    g, gL = level_grid(wl, level), level_grid(wl, finest_level)
+    m, mL, T = wl["steps"][level], wl["steps"][finest_level], wl["T"]
+    rows = [initial_state(wl, g)] + list(U)
+    out = np.empty((mL, gL.n))
+    for k in range(1, mL + 1):
+        pos = k * m / mL  # in steps of the level
+        j = int(np.floor(pos + 1e-12))
+        w = pos - j
+        if w < 1e-12:
+            out[k - 1] = mlmc.interpolate(g, rows[j], gL)
+        else:
+            out[k - 1] = (1 - w) * mlmc.interpolate(g, rows[j], gL) + w * mlmc.interpolate(g, rows[j + 1], gL)
+    return out.ravel()
+
+
+def space_time_weights(wl, finest_level):
+    """Quadrature of L^2(0, T; L^2(D)) on the finest time levels 1 .. m_L:
+    lumped weights in space times the trapezoid rule in time (the t = 0
+    level, the deterministic initial state, carries no variance)."""
+    gL = level_grid(wl, finest_level)
+    mL = wl["steps"][finest_level]
+    dt = wl["T"] / mL
+    wt = np.full(mL, dt)
+    wt[-1] = 0.5 * dt
+    return (wt[:, None] * gL.lumped_weights()[None, :]).ravel()
+
+
 def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
-    """MLMC mean/variance of the activation map on the finest grid.
+    """MLMC mean/variance on the finest grid of the workload's QoI: the
+    activation map (qoi 'activation', the default) or the space-time
+    solution u on the finest space-time grid (qoi 'spacetime', the paper's
+    E[u] of Sec. 4.1, with V_l in the L^2(0, T; L^2(D)) sense).
 
     N[l] samples on level l; xi_levels[l] (N[l], M) are the inputs shared by
     the fine (level l) and coarse (level l-1) member of each pair;
@@ -138,12 +173,16 @@ def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
     """
     L1 = len(N)
     finest = level_grid(wl, L1 - 1)
-    weights = finest.lumped_weights()
+    spacetime = wl.get("qoi", "activation") == "spacetime"
+    weights = space_time_weights(wl, L1 - 1) if spacetime else finest.lumped_weights()
+    vol = finest.volume() * wl["T"] if spacetime else None
     fine_q, coarse_q = [], []
 
     def level_qoi(lv, xi):
         sig = kl_synthesize(modes_levels[lv], xi, wl["sigma_f0"], wl.get("field", "lognormal"))
         U, _ = st_solve(wl, lv, sig, mode=solve_mode)
+        if spacetime:
+            return np.array([space_time_sample(wl, lv, Us, L1 - 1) for Us in U])
         t, _ = activation_map(wl, lv, U)
         g = level_grid(wl, lv)
         return np.array([mlmc.interpolate(g, ti, finest) for ti in t])
@@ -152,7 +191,7 @@ def mlmc_estimate(wl, N, xi_levels, modes_levels, solve_mode="block"):
         xi = np.asarray(xi_levels[l])[: N[l]]
         fine_q.append(level_qoi(l, xi))
         coarse_q.append(level_qoi(l - 1, xi) if l > 0 else None)
-    out = mlmc.mlmc_combine(fine_q, coarse_q, weights)
+    out = mlmc.mlmc_combine(fine_q, coarse_q, weights, vol)
     out["fine_q"] = fine_q
     out["coarse_q"] = coarse_q
     return out

@@ -91,7 +91,7 @@ class Welford:
 
 # -- MLMC combination -------------------------------------------------------
 
-def mlmc_combine(fine_q, coarse_q, weights):
+def mlmc_combine(fine_q, coarse_q, weights, vol=None):
     """Combine per-level samples already interpolated to the finest grid.
 
     fine_q[l]   : (N_l, n_L) samples of P Q_l
@@ -100,10 +100,11 @@ def mlmc_combine(fine_q, coarse_q, weights):
     weights     : (n_L,) quadrature weights of the finest grid
 
     Returns dict: mean, var (n_L,), level_mean, level_var (Y_l fields),
-    V (per-level scalar |D|^-1 int s^2(Y_l)), counts.
+    V (per-level scalar |D|^-1 int s^2(Y_l)), counts.  vol: the measure the
+    integral is divided by (default: the sum of the weights).
     """
     L1 = len(fine_q)
-    vol = weights.sum()
+    vol = weights.sum() if vol is None else vol
     mean = 0.0
     var = 0.0
     level_mean, level_var, V = [], [], []

@@ -69,6 +69,7 @@ def problem_from_workload(wl, **overrides):
     p.field_kind = _lib.FIELD_KINDS[wl.get("field", "lognormal")]
     p.tau_relative = int(wl.get("tau_relative", 0))
     p.ic_kind = _lib.IC_KINDS[wl.get("ic_kind", "ball")]
+    p.qoi = _lib.QOIS[wl.get("qoi", "activation")]
     prec = overrides.pop("precision", wl.get("precision", "fp64"))
     p.precision = _lib.PRECISIONS[prec]
     for k, v in overrides.items():
@@ -206,10 +207,11 @@ class Context:
             _check_dev(modes[l], "modes[%d]" % l, torch.float64, (self.sizes[l][1], M))
             _check_dev(xi[l], "xi[%d]" % l, torch.float64, (xi[l].shape[0], M))
         dev = modes[0].device
-        mean = torch.empty(nL, dtype=torch.float64, device=dev)
-        var = torch.empty(nL, dtype=torch.float64, device=dev)
-        lmean = torch.empty((L1, nL), dtype=torch.float64, device=dev) if level_fields else None
-        lvar = torch.empty((L1, nL), dtype=torch.float64, device=dev) if level_fields else None
+        P = nL * (self.sizes[-1][2] if self.problem.qoi == _lib.QOIS["spacetime"] else 1)
+        mean = torch.empty(P, dtype=torch.float64, device=dev)
+        var = torch.empty(P, dtype=torch.float64, device=dev)
+        lmean = torch.empty((L1, P), dtype=torch.float64, device=dev) if level_fields else None
+        lvar = torch.empty((L1, P), dtype=torch.float64, device=dev) if level_fields else None
         res = _lib.StmMlmcResult()
         res.mean, res.var = mean.data_ptr(), var.data_ptr()
         res.level_mean = lmean.data_ptr() if lmean is not None else None

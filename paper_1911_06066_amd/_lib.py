@@ -19,6 +19,7 @@ FIBER_LAWS = {"diag2d": 0, "rot3d": 1, "x": 2, "diag": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 FIELD_KINDS = {"lognormal": 0, "additive": 1}
 IC_KINDS = {"ball": 0, "gauss": 1}
+QOIS = {"activation": 0, "spacetime": 1}
 
 
 class StmLevel(ctypes.Structure):
@@ -59,6 +60,7 @@ class StmProblem(ctypes.Structure):
         ("field_kind", ctypes.c_int),
         ("tau_relative", ctypes.c_int),
         ("ic_kind", ctypes.c_int),
+        ("qoi", ctypes.c_int),
     ]
 
 

@@ -141,24 +141,46 @@ hipError_t launch_prolong_st(const GridDev& gc, const GridDev& gf, int dim, int 
   return hipGetLastError();
 }
 
+// Number of QoI points: the finest nodes, or the finest space-time points.
+__device__ __host__ __forceinline__ int64_t qoi_points(const StatsLevelArgs& a) {
+  return a.mL ? (int64_t)a.mL * a.gL.n : (int64_t)a.gL.n;
+}
+
+// Sample s of a level's QoI at QoI point q: the nested Q1 interpolant of its
+// activation map, or of its space-time solution at finest time level k + 1
+// (q = k n_L + p), linear in time between the level's bracketing time levels,
+// time level 0 being the level's initial state.
+__device__ __forceinline__ double qoi_value(const StatsLevelArgs& a, const GridDev& g, int m, const double* f,
+                                            const double* u0, int s, int q) {
+  if (a.mL == 0) return interp_nested(g, a.gL, a.dim, f + (int64_t)s * g.n, q);
+  const int p = q % a.gL.n, k = q / a.gL.n;
+  const int64_t num = (int64_t)(k + 1) * m;
+  const int j = (int)(num / a.mL);
+  const double w = double(num % a.mL) / a.mL;
+  const double* us = f + (int64_t)s * m * g.n;
+  const double lo = interp_nested(g, a.gL, a.dim, j == 0 ? u0 : us + (int64_t)(j - 1) * g.n, p);
+  const double hi = (w > 0.0) ? interp_nested(g, a.gL, a.dim, us + (int64_t)j * g.n, p) : 0.0;
+  return (1.0 - w) * lo + w * hi;
+}
+
 // Pass 1: Welford over each chunk of samples. part[c][0..5][p]: mean_f, M2_f, mean_c, M2_c, mean_y, M2_y.
 __global__ void level_chunk_kernel(StatsLevelArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
-  if (p >= a.gL.n) return;
+  if (p >= qoi_points(a)) return;
   const int s0 = c * a.chunk, s1 = min(a.N, s0 + a.chunk);
   double mf = 0, qf2 = 0, mc = 0, qc2 = 0, my = 0, qy2 = 0;
   int cnt = 0;
   for (int s = s0; s < s1; ++s) {
-    const double vf = interp_nested(a.gf, a.gL, a.dim, a.tf + (int64_t)s * a.gf.n, p);
-    const double vc = a.tc ? interp_nested(a.gc, a.gL, a.dim, a.tc + (int64_t)s * a.gc.n, p) : 0.0;
+    const double vf = qoi_value(a, a.gf, a.mf, a.tf, a.u0f, s, p);
+    const double vc = a.tc ? qoi_value(a, a.gc, a.mc, a.tc, a.u0c, s, p) : 0.0;
     const double vy = vf - vc;
     ++cnt;
     double d = vf - mf; mf += d / cnt; qf2 += d * (vf - mf);
     d = vc - mc; mc += d / cnt; qc2 += d * (vc - mc);
     d = vy - my; my += d / cnt; qy2 += d * (vy - my);
   }
-  const int64_t n = a.gL.n;
+  const int64_t n = qoi_points(a);
   double* q = a.part + (int64_t)c * 6 * n + p;
   q[0] = mf; q[n] = qf2; q[2 * n] = mc; q[3 * n] = qc2; q[4 * n] = my; q[5 * n] = qy2;
 }
@@ -167,9 +189,9 @@ __global__ void level_chunk_kernel(StatsLevelArgs a) {
 // write the level fields, and per-block partial sums of w_p s^2(Y_l)(p).
 __global__ void level_merge_kernel(StatsLevelArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = a.gL.n;
+  const int64_t n = qoi_points(a);
   double contrib = 0.0;
-  if (p < a.gL.n) {
+  if (p < n) {
     const int nch = (a.N + a.chunk - 1) / a.chunk;
     double cnt = 0, mf = 0, qf2 = 0, mc = 0, qc2 = 0, my = 0, qy2 = 0;
     for (int c = 0; c < nch; ++c) {
@@ -187,14 +209,17 @@ __global__ void level_merge_kernel(StatsLevelArgs a) {
     a.var[p] += vf - (a.tc ? vc : 0.0);
     if (a.level_mean) a.level_mean[p] = my;
     if (a.level_var) a.level_var[p] = vy;
-    // lumped (trapezoid) weight of the finest node
-    const int ix = p % a.gL.nx;
-    const int r = p / a.gL.nx;
+    // lumped (trapezoid) weight of the finest node, times the trapezoid
+    // weight in time of the space-time point (the t = 0 level has no variance)
+    const int pn = a.mL ? p % a.gL.n : p;
+    const int ix = pn % a.gL.nx;
+    const int r = pn / a.gL.nx;
     const int iy = (a.dim == 2) ? r : r % a.gL.ny;
     const int iz = (a.dim == 2) ? 0 : r / a.gL.ny;
     double w = a.gL.hx * a.gL.hy * ((ix == 0 || ix == a.gL.nx - 1) ? 0.5 : 1.0) *
                ((iy == 0 || iy == a.gL.ny - 1) ? 0.5 : 1.0);
     if (a.dim == 3) w *= a.gL.hz * ((iz == 0 || iz == a.gL.nz - 1) ? 0.5 : 1.0);
+    if (a.mL) w *= (p / a.gL.n == a.mL - 1) ? 0.5 * a.dtL : a.dtL;
     contrib = w * vy;
   }
   __shared__ double sh[256];
@@ -210,11 +235,13 @@ __global__ void level_merge_kernel(StatsLevelArgs a) {
 hipError_t launch_level_stats(const StatsLevelArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipErrorInvalidValue;
   const int nch = (a.N + a.chunk - 1) / a.chunk;
-  dim3 g1((a.gL.n + 255) / 256, nch);
+  const int64_t P = qoi_points(a);
+  if (P >= ((int64_t)1 << 31) - 256) return hipErrorInvalidValue;
+  dim3 g1((unsigned)((P + 255) / 256), nch);
   hipLaunchKernelGGL(level_chunk_kernel, g1, dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(level_merge_kernel, dim3((a.gL.n + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(level_merge_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

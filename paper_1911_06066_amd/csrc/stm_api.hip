@@ -149,6 +149,7 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
     return fail(c, STM_E_INVALID, "field_kind must be 0 (lognormal) or 1 (additive)");
   if (p.tau_relative != 0 && p.tau_relative != 1) return fail(c, STM_E_INVALID, "tau_relative must be 0 or 1");
   if (p.ic_kind != STM_IC_BALL && p.ic_kind != STM_IC_GAUSS) return fail(c, STM_E_INVALID, "ic_kind must be 0 or 1");
+  if (p.qoi != STM_QOI_ACTIVATION && p.qoi != STM_QOI_SPACETIME) return fail(c, STM_E_INVALID, "qoi must be 0 or 1");
   if (p.ic_kind == STM_IC_GAUSS && !(p.ic_radius > 0))
     return fail(c, STM_E_INVALID, "the Gaussian initial state needs ic_radius > 0");
   if (!(p.theta == 0 || (p.theta >= 0.5 && p.theta <= 1.0)))
@@ -159,7 +160,7 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
   for (int l = 0; l < p.n_levels; ++l) {
     const stm_level& L = p.levels[l];
     const int nz = p.dim == 3 ? L.nz : 1;
-    if (L.nx < 3 || L.ny < 3 || (p.dim == 3 && L.nz < 2) || L.m < 1)
+    if (L.nx < 3 || L.ny < 2 || (p.dim == 3 && (L.ny < 3 || L.nz < 2)) || L.m < 1)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
     if (L.smooth_sweeps < 0 || L.smooth_sweeps > kMaxSweeps || !(L.cheb_ratio == 0 || L.cheb_ratio > 1))
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": smooth_sweeps in 0..32, cheb_ratio 0 or > 1");
@@ -172,8 +173,10 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
       return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": grid too large for 32-bit index arithmetic");
     if (l > 0) {
       const stm_level& P = p.levels[l - 1];
-      if (L.nx != 2 * P.nx - 1 || L.ny != 2 * P.ny - 1 || (p.dim == 3 && L.nz != 2 * P.nz - 1))
-        return fail(c, STM_E_INVALID, "levels must be nested 2:1 refinements");
+      // every axis refined 2:1 or kept (a strip keeps its single element row)
+      auto nested = [](int f, int c0) { return f == 2 * c0 - 1 || f == c0; };
+      if (!nested(L.nx, P.nx) || !nested(L.ny, P.ny) || (p.dim == 3 && !nested(L.nz, P.nz)))
+        return fail(c, STM_E_INVALID, "levels must be nested: each axis refined 2:1 or kept");
     }
   }
   return STM_OK;
@@ -829,24 +832,32 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
   }
   const LevelDev& dL = c->levels[L1 - 1].dev;
   const int nL = dL.g[0].n;
-  // device buffers: sigma and activation maps of every sample (fine and coarse members)
-  std::vector<size_t> off_sf(L1), off_sc(L1), off_tf(L1), off_tc(L1);
+  const bool st_qoi = c->p.qoi == STM_QOI_SPACETIME;
+  const size_t P = st_qoi ? (size_t)dL.m * nL : (size_t)nL;  // QoI points on the finest (space-time) grid
+  if (P >= ((size_t)1 << 31) - 256) return fail(c, STM_E_UNSUPPORTED, "too many QoI points for one launch");
+  // device buffers: sigma and activation maps of every sample (fine and coarse
+  // members), and for the space-time QoI their solutions
+  std::vector<size_t> off_sf(L1), off_sc(L1), off_tf(L1), off_tc(L1), off_uf(L1, 0), off_uc(L1, 0);
   size_t tot = 0;
   for (int l = 0; l < L1; ++l) {
-    const int nf = c->levels[l].dev.g[0].n, ef = c->levels[l].dev.g[0].ne;
+    const LevelDev& df = c->levels[l].dev;
+    const int nf = df.g[0].n, ef = df.g[0].ne;
     off_sf[l] = tot; tot += (size_t)cap[l] * ef;
     off_tf[l] = tot; tot += (size_t)cap[l] * nf;
+    if (st_qoi) { off_uf[l] = tot; tot += (size_t)cap[l] * df.m * nf; }
     if (l > 0) {
-      const int nc = c->levels[l - 1].dev.g[0].n, ec = c->levels[l - 1].dev.g[0].ne;
+      const LevelDev& dc = c->levels[l - 1].dev;
+      const int nc = dc.g[0].n, ec = dc.g[0].ne;
       off_sc[l] = tot; tot += (size_t)cap[l] * ec;
       off_tc[l] = tot; tot += (size_t)cap[l] * nc;
+      if (st_qoi) { off_uc[l] = tot; tot += (size_t)cap[l] * dc.m * nc; }
     }
   }
   int max_cap = 0;
   for (int l = 0; l < L1; ++l) max_cap = std::max(max_cap, cap[l]);
   const int chunk = 64;
-  const size_t part_sz = (size_t)((max_cap + chunk - 1) / chunk) * 6 * nL;
-  const size_t vpart_sz = (size_t)(nL + 255) / 256;
+  const size_t part_sz = (size_t)((max_cap + chunk - 1) / chunk) * 6 * P;
+  const size_t vpart_sz = (P + 255) / 256;
   const size_t off_part = tot; tot += part_sz;
   const size_t off_vpart = tot; tot += vpart_sz;
   if ((st = grow(c, &c->d_scratch, &c->scratch_cap, tot * sizeof(double)))) return st;
@@ -930,7 +941,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         t.stride = g.lanes;
         t.count = (N - i + g.lanes - 1) / g.lanes;
         t.sigma = S0 + (g.coarse ? off_sc[l] : off_sf[l]);
-        t.u_out = nullptr;
+        t.u_out = st_qoi ? S0 + (g.coarse ? off_uc[l] : off_uf[l]) : nullptr;
         t.u_guess = nullptr;
         t.t_act = S0 + (g.coarse ? off_tc[l] : off_tf[l]);
         t.work = static_cast<unsigned char*>(c->work) + woff;
@@ -964,11 +975,11 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       // level fields are still needed internally only as scalars
     }
     if ((st = timed_begin(c))) return st;
-    hipError_t e = launch_fill(out->mean, 0.0, nL, c->stream);
-    if (e == hipSuccess) e = launch_fill(out->var, 0.0, nL, c->stream);
+    hipError_t e = launch_fill(out->mean, 0.0, (int64_t)P, c->stream);
+    if (e == hipSuccess) e = launch_fill(out->var, 0.0, (int64_t)P, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "fill");
     std::vector<double> vpart(vpart_sz);
-    double vol = c->p.lx * c->p.ly * (c->p.dim == 3 ? c->p.lz : 1.0);
+    double vol = c->p.lx * c->p.ly * (c->p.dim == 3 ? c->p.lz : 1.0) * (st_qoi ? c->p.T : 1.0);
     for (int l = 0; l < L1; ++l) {
       StatsLevelArgs a{};
       a.gf = c->levels[l].dev.g[0];
@@ -982,9 +993,19 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       a.part = S0 + off_part;
       a.mean = out->mean;
       a.var = out->var;
-      a.level_mean = out->level_mean ? out->level_mean + (size_t)l * nL : nullptr;
-      a.level_var = out->level_var ? out->level_var + (size_t)l * nL : nullptr;
+      a.level_mean = out->level_mean ? out->level_mean + (size_t)l * P : nullptr;
+      a.level_var = out->level_var ? out->level_var + (size_t)l * P : nullptr;
       a.vpart = S0 + off_vpart;
+      if (st_qoi) {
+        a.tf = S0 + off_uf[l];
+        a.tc = l > 0 ? S0 + off_uc[l] : nullptr;
+        a.mf = c->levels[l].dev.m;
+        a.mc = l > 0 ? c->levels[l - 1].dev.m : 0;
+        a.mL = dL.m;
+        a.dtL = dL.dt;
+        a.u0f = c->levels[l].dev.u0;
+        a.u0c = l > 0 ? c->levels[l - 1].dev.u0 : nullptr;
+      }
       e = launch_level_stats(a, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "stats launch");
       if (l == L1 - 1) {
@@ -999,12 +1020,12 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
     }
     // per-level mean norms for the bias estimate
     if (out->level_mean) {
-      std::vector<double> lm(nL);
+      std::vector<double> lm(P);
       for (int l = 0; l < L1; ++l) {
-        STM_HIP(c, hipMemcpy(lm.data(), out->level_mean + (size_t)l * nL, nL * sizeof(double), hipMemcpyDeviceToHost));
+        STM_HIP(c, hipMemcpy(lm.data(), out->level_mean + (size_t)l * P, P * sizeof(double), hipMemcpyDeviceToHost));
         double s2 = 0.0;
         for (double v : lm) s2 += v * v;
-        level_norm[l] = std::sqrt(s2 / nL);
+        level_norm[l] = std::sqrt(s2 / (double)P);
       }
     }
     STM_HIP(c, hipMemcpy(sh.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));

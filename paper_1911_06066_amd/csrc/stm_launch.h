@@ -48,7 +48,14 @@ struct StatsLevelArgs {
   double* var;           // [gL.n] accumulated MLMC variance
   double* level_mean;    // [gL.n] or null
   double* level_var;     // [gL.n] or null
-  double* vpart;         // [ceil(gL.n / 256)] partial sums of w_p s^2(Y_l)
+  double* vpart;         // [ceil(P / 256)] partial sums of w_p s^2(Y_l)
+  // space-time QoI (mL > 0): tf/tc hold [N][m][g.n] solutions, the points are
+  // the finest grid's time levels 1 .. mL, P = mL gL.n; u0f/u0c: the levels'
+  // initial states (time level 0)
+  int mf, mc, mL;
+  double dtL;
+  const double* u0f;
+  const double* u0c;
 };
 hipError_t launch_level_stats(const StatsLevelArgs& a, hipStream_t st);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);

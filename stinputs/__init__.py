@@ -17,6 +17,9 @@ grid whose element counts are 64 x 64 x 16 etc.):
                 (ell 0.15, s2 0.2), 256 samples, mixed precision
   mlmc5_3d      five 3D levels 9x9x3 ... 129x129x33 nodes, 32 ... 512 steps,
                 128 modes, sample counts chosen adaptively
+  cable1d       the 1D+1 hierarchy of Table 1 as a strip of one element row:
+                31 2^l elements of 0.032 / 2^l cm, 4 2^l steps of 0.16 / 2^l ms,
+                the cube's physics and field, space-time QoI E[u]
   cube4_3d      the paper's cube: [0,1]^3 cm, 6^3 ... 41^3 nodes, 24 ... 192
                 steps to 0.96 ms, isotropic additive uniform field (Gaussian
                 kernel, 66 modes), 1024/256/64/16 pairs, FP64
@@ -122,6 +125,16 @@ WORKLOADS = {
                    levels=[(6, 6, 6), (11, 11, 11), (21, 21, 21), (41, 41, 41)],
                    steps=[24, 48, 96, 192], n_modes=66, kl_grid=(41, 41, 41),
                    samples=[1024, 256, 64, 16], precision="fp64"),
+    # the 1D+1 study (Sec. 4.1, Table 1): the interval of 31 elements of
+    # h = 0.032 cm, refined 2:1 in space and time; a 2D strip one element
+    # high (as high as the finest element is long) whose data do not depend
+    # on y solves the 1D problem exactly -- the stimulus is centred on the
+    # strip's midline, so both node rows see the same initial state
+    "cable1d": _w(_CUBE_3D, name="cable1d", dim=2, lengths=(0.992, 0.004), T=0.64,
+                  ic_center=(0.0, 0.002), ic_radius=0.25,
+                  levels=[(32, 2), (63, 2), (125, 2), (249, 2)], steps=[4, 8, 16, 32],
+                  n_modes=16, kl_grid=(249, 2), samples=[4096, 256, 16, 2], qoi="spacetime",
+                  precision="fp64"),
 }
 
 WORKLOAD_IDS = {name: i for i, name in enumerate(WORKLOADS)}

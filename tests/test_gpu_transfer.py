@@ -67,3 +67,36 @@ def test_prolonged_coarse_solution_as_first_iterate(torch_dev, workload):
     u2, st2 = ctx.st_solve(1, sf, u0_guess=guess)
     assert all(s["status"] == 0 for s in st1 + st2)
     assert _rel(u2.cpu().numpy(), u1.cpu().numpy()) < 1e-9
+
+
+@pytest.mark.parametrize("case", ["2d", "strip"])
+def test_space_time_qoi_mlmc_matches_oracle(torch_dev, case):
+    """E[u] on the finest space-time grid (Sec. 4.1): mean, variance, level
+    fields and V_l in the L^2(0, T; L^2(D)) sense against the oracle."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    if case == "2d":
+        wl = stinputs.workload("small_mc_2d", levels=[(9, 9), (17, 17), (33, 33)], steps=[6, 12, 24],
+                               n_modes=8, kl_grid=(17, 17), ic_radius=0.25, sigma_f0=4e-3, qoi="spacetime")
+        N = [8, 4, 3]
+    else:
+        wl = stinputs.workload("cable1d", levels=[(32, 2), (63, 2), (125, 2)], steps=[4, 8, 16],
+                               kl_grid=(125, 2))
+        N = [16, 8, 4]
+    basis = oapi.kl_basis(wl)
+    modes = [oapi.kl_modes(wl, l, basis) for l in range(3)]
+    xi = [stinputs.xi(wl["name"], l, N[l], wl["n_modes"]) for l in range(3)]
+    ctx = Context(wl)
+    out = ctx.mlmc_estimate(N, [torch.from_numpy(m).to(dev) for m in modes],
+                            [torch.from_numpy(x).to(dev) for x in xi])
+    ref = oapi.mlmc_estimate(wl, N, xi, modes, solve_mode="timestep")
+    mean = out["mean"].cpu().numpy()
+    assert mean.shape == ref["mean"].shape == (wl["steps"][-1] * ctx.sizes[-1][0],)
+    assert np.abs(mean - ref["mean"]).max() <= 1e-9 * np.abs(ref["mean"]).max()
+    rv = ref["var"]
+    assert np.abs(out["var"].cpu().numpy() - rv).max() <= 1e-9 * np.abs(rv).max()
+    np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8)
+    lm = out["level_mean"].cpu().numpy()
+    for l in range(3):
+        assert np.abs(lm[l] - ref["level_mean"][l]).max() <= 1e-9 * np.abs(ref["mean"]).max()
+    assert out["worst_status"] == 0

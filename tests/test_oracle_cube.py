@@ -280,3 +280,78 @@ def test_space_time_prolongation_time_weights():
         expect = np.interp(t, np.arange(mc + 1), np.concatenate([[1.0], 2.0 * np.arange(1, mc + 1)]))
         np.testing.assert_allclose(Uf[:, 0], expect, rtol=0, atol=1e-14)
         np.testing.assert_allclose(Uf, Uf[:, :1].repeat(25, axis=1), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Space-time QoI and the 1D+1 strip (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def test_space_time_sample_is_exact_on_multilinear_fields():
+    """A level's solution sampled from f(x, t) = (multilinear in x) + t (linear
+    in x), with the level's initial state f(x, 0), maps onto the finest
+    space-time grid as f itself."""
+    wl = stinputs.workload("small_mc_2d", levels=[(5, 4), (9, 7), (17, 13)], steps=[3, 6, 12], lengths=(1.0, 0.6))
+    f = lambda x, t: 0.3 + 0.7 * x[:, 0] - 1.1 * x[:, 1] + 0.4 * x[:, 0] * x[:, 1] + t * (0.5 - 0.2 * x[:, 0])
+    T = wl["T"]
+    import oracle.api as oa
+    saved = oa.initial_state
+    oa.initial_state = lambda w, g: f(g.nodes(), 0.0)
+    try:
+        gL = api.level_grid(wl, 2)
+        expect = np.concatenate([f(gL.nodes(), (k + 1) * T / 12) for k in range(12)])
+        for l in range(3):
+            g = api.level_grid(wl, l)
+            m = wl["steps"][l]
+            U = np.stack([f(g.nodes(), (j + 1) * T / m) for j in range(m)])
+            np.testing.assert_allclose(oa.space_time_sample(wl, l, U, 2), expect, rtol=0, atol=1e-13)
+    finally:
+        oa.initial_state = saved
+
+
+def test_space_time_weights_integrate_in_time_and_space():
+    wl = stinputs.workload("cable1d")
+    w = api.space_time_weights(wl, 3)
+    g = api.level_grid(wl, 3)
+    dt = wl["T"] / wl["steps"][3]
+    np.testing.assert_allclose(w.sum(), g.volume() * (wl["T"] - 0.5 * dt), rtol=1e-13)
+    # linear in t over the time levels 1 .. m: trapezoid with the t = 0 value 0 is exact
+    t = np.repeat(np.arange(1, wl["steps"][3] + 1) * dt, g.n)
+    np.testing.assert_allclose(w @ t, g.volume() * wl["T"] ** 2 / 2, rtol=1e-13)
+
+
+def test_strip_of_one_element_row_is_the_1d_problem():
+    """On y-constant vectors the strip's Q1 mass and isotropic stiffness are
+    (l_y / 2) times the 1D Q1 matrices (h/6 [2 1; 1 2], sigma/h [1 -1; -1 1])
+    at each of the two node rows, so the strip solves the 1D equations."""
+    wl = stinputs.workload("cable1d")
+    g = api.level_grid(wl, 0)
+    nx = g.shape[0]
+    hx, ly = g.h[0], wl["lengths"][1]
+    rng = np.random.default_rng(11)
+    sigma = rng.uniform(0.5, 1.5, nx - 1)
+    D = fem.diffusion_tensors(sigma, np.zeros(nx - 1), 0.0, 2, tau_rel=1.0)
+    M = fem.assemble_mass(g).toarray()
+    K = fem.assemble_stiffness(g, D).toarray()
+    M1, K1 = np.zeros((nx, nx)), np.zeros((nx, nx))
+    for e in range(nx - 1):
+        M1[e:e + 2, e:e + 2] += hx / 6 * np.array([[2, 1], [1, 2]])
+        K1[e:e + 2, e:e + 2] += sigma[e] / hx * np.array([[1, -1], [-1, 1]])
+    v = rng.uniform(-1, 1, nx)
+    vv = np.concatenate([v, v])
+    for A, A1 in ((M, M1), (K, K1)):
+        r = A @ vv
+        ref = 0.5 * ly * (A1 @ v)
+        tol = 1e-11 * np.abs(ref).max()  # rounding of sums with cancellation
+        np.testing.assert_allclose(r[:nx], ref, rtol=0, atol=tol)
+        np.testing.assert_allclose(r[nx:], r[:nx], rtol=0, atol=tol)
+
+
+def test_strip_solution_does_not_depend_on_y():
+    wl = stinputs.workload("cable1d")
+    b = api.kl_basis(wl)
+    m = api.kl_modes(wl, 1, b)
+    sig = api.kl_synthesize(m, stinputs.xi("cable1d", 1, 1, 16), wl["sigma_f0"], "additive")
+    U, st = api.st_solve(wl, 1, sig, mode="timestep")
+    nx = wl["levels"][1][0]
+    np.testing.assert_allclose(U[0][:, nx:], U[0][:, :nx], rtol=0, atol=1e-12)
+    assert st[0].converged
