@@ -95,7 +95,12 @@ def test_space_time_qoi_mlmc_matches_oracle(torch_dev, case):
     assert np.abs(mean - ref["mean"]).max() <= 1e-9 * np.abs(ref["mean"]).max()
     rv = ref["var"]
     assert np.abs(out["var"].cpu().numpy() - rv).max() <= 1e-9 * np.abs(rv).max()
-    np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8)
+    # V_l = (|D| T)^-1 int int s^2(Y_l): with both solutions within ~1e-10 of
+    # the exact discrete ones (Newton tolerance on u = O(1)), Y_l moves by at
+    # most ~2e-10 and V_l by ~4e-10 sqrt(V_l) -- which matters for the tiny
+    # level corrections of the linear 1D problem
+    V, Vr = np.asarray(out["V"]), np.asarray(ref["V"])
+    assert np.all(np.abs(V - Vr) <= 4e-10 * np.sqrt(Vr) + 1e-8 * Vr + 1e-20), (V, Vr)
     lm = out["level_mean"].cpu().numpy()
     for l in range(3):
         assert np.abs(lm[l] - ref["level_mean"][l]).max() <= 1e-9 * np.abs(ref["mean"]).max()
