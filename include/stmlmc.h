@@ -97,8 +97,9 @@ typedef struct {
 
 /*
  * The problem: monodomain equation du/dt = div(D grad u) + f(u) on the box
- * [0,lx] x [0,ly] (x [0,lz]) with homogeneous Neumann boundaries, backward
- * Euler in time on [0,T], Q1 elements in space (Sec. 2.1, Sec. 3.2).
+ * [0,lx] x [0,ly] (x [0,lz]) with homogeneous Neumann boundaries, the theta
+ * scheme in time on [0,T] (backward Euler or the paper's Crank-Nicolson, see
+ * theta), Q1 elements in space (Sec. 2.1, Sec. 3.2).
  *   f(u) = k_react u (u - a_react)(1 - u)       (FitzHugh-Nagumo cubic, eq. ionic_term)
  *   D_e  = sigma_e a a^T + tau_e (I - a a^T),
  *          tau_e = transverse_ratio sigma_f0 (tau_relative = 0) or transverse_ratio sigma_e (= 1;

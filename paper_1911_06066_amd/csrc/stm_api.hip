@@ -150,6 +150,7 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
   if (p.tau_relative != 0 && p.tau_relative != 1) return fail(c, STM_E_INVALID, "tau_relative must be 0 or 1");
   if (p.ic_kind != STM_IC_BALL && p.ic_kind != STM_IC_GAUSS) return fail(c, STM_E_INVALID, "ic_kind must be 0 or 1");
   if (p.qoi != STM_QOI_ACTIVATION && p.qoi != STM_QOI_SPACETIME) return fail(c, STM_E_INVALID, "qoi must be 0 or 1");
+  if (!(p.ic_radius >= 0)) return fail(c, STM_E_INVALID, "ic_radius must be >= 0");
   if (p.ic_kind == STM_IC_GAUSS && !(p.ic_radius > 0))
     return fail(c, STM_E_INVALID, "the Gaussian initial state needs ic_radius > 0");
   if (!(p.theta == 0 || (p.theta >= 0.5 && p.theta <= 1.0)))

@@ -74,6 +74,7 @@ def test_struct_layouts_match_header(cname, pyname):
 @pytest.mark.parametrize("field,value", [
     ("dim", 4), ("n_levels", 0), ("n_modes", 0), ("precision", 7), ("gmres_restart", 31),
     ("block_threads", 100), ("fiber_law", 9), ("theta", 0.3), ("theta", 1.5),
+    ("field_kind", 2), ("tau_relative", 3), ("ic_kind", 5), ("qoi", 2), ("ic_radius", -1.0),
 ])
 def test_invalid_problem_rejected_before_device_work(field, value):
     L, lib = _lib()
@@ -83,6 +84,14 @@ def test_invalid_problem_rejected_before_device_work(field, value):
     h = ctypes.c_void_p()
     st = lib.stm_create(ctypes.byref(p), None, ctypes.byref(h))
     assert st == -1 and not h.value
+
+
+def test_gaussian_initial_state_needs_a_radius():
+    L, lib = _lib()
+    from paper_1911_06066_amd import problem_from_workload
+    p = problem_from_workload(stinputs.workload("cube4_3d", ic_radius=0.0))
+    h = ctypes.c_void_p()
+    assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
 
 
 def test_multigrid_variant_is_refused():
