@@ -664,7 +664,9 @@ stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, dou
   int* cen = nullptr;
   if (n_censored_host) {
     if ((st = grow(c, &c->d_int, &c->int_cap, (size_t)S * sizeof(int)))) return st;
-    STM_HIP(c, hipMemsetAsync(c->d_int, 0, S * sizeof(int), c->stream));
+    // a fill kernel rather than a memset node, so that the call stays correct under graph capture
+    const hipError_t fe = launch_fill_u32(reinterpret_cast<unsigned*>(c->d_int), 0u, (int64_t)S, c->stream);
+    if (fe != hipSuccess) return hip_fail(c, fe, "fill");
     cen = c->d_int;
   }
   reset_timings(c);
