@@ -73,6 +73,27 @@ __global__ void fill_u32_kernel(unsigned* p, unsigned v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+// out[s] = min_e a[s][e]: one block per row
+__global__ void row_min_kernel(const double* __restrict__ a, int E, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const double* r = a + (int64_t)blockIdx.x * E;
+  double v = 1.0e300;
+  for (int e = threadIdx.x; e < E; e += 256) v = fmin(v, r[e]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+hipError_t launch_row_min(const double* a, int S, int E, double* out, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_min_kernel, dim3(S), dim3(256), 0, st, a, E, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);

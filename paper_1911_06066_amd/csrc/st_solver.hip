@@ -805,7 +805,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   const double* prevU = nullptr;
 
   for (int it_s = 0; it_s < task.count; ++it_s) {
-    const int s = task.first + it_s * task.stride;
+    const int s = task.order ? task.order[task.first + it_s * task.stride] : task.first + it_s * task.stride;
     const long long t_start = wall_clock64();
     tm.bytes = 0.0;
     tm.sigma = task.sigma + (int64_t)s * g0.ne;

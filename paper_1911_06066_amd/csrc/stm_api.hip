@@ -51,12 +51,19 @@ struct stm_ctx {
   size_t scratch_cap = 0;
   unsigned char* d_sync = nullptr;
   size_t sync_cap = 0;
+  int* d_order = nullptr;        // sample order of split groups (MLMC launch)
+  size_t order_cap = 0;
+  double* d_rowmin = nullptr;    // per-sample minimum conductivity (MLMC launch)
+  size_t rowmin_cap = 0;
   // phase timing
   hipEvent_t ev[2] = {nullptr, nullptr};
   stm_timings tm{};
   // measured mean device seconds per sample of each level with a team of G
   // workgroups, tsec[level][G] (0 = not measured yet)
   double tsec[STM_MAX_LEVELS][kMaxTeam + 1] = {};
+  // device seconds of the predicted-hard samples of a grid relative to the
+  // others at the same team size (measured after every launch that splits)
+  double hard_ratio[STM_MAX_LEVELS] = {1.3, 1.3, 1.3, 1.3, 1.3, 1.3, 1.3, 1.3};
   int stage_bytes = 48 * 1024;   // dynamic LDS per solver workgroup
 };
 
@@ -549,6 +556,8 @@ void stm_destroy(stm_ctx* c) {
   if (c->d_tasks) (void)hipFree(c->d_tasks);
   if (c->d_stats) (void)hipFree(c->d_stats);
   if (c->d_int) (void)hipFree(c->d_int);
+  if (c->d_order) (void)hipFree(c->d_order);
+  if (c->d_rowmin) (void)hipFree(c->d_rowmin);
   if (c->d_scratch) (void)hipFree(c->d_scratch);
   if (c->d_sync) (void)hipFree(c->d_sync);
   for (auto& e : c->ev)
@@ -712,6 +721,9 @@ struct Group {          // all fine or all coarse members of one MLMC level
   int mlmc_level;
   bool coarse;
   int n0, n1;           // samples [n0, n1) solved in this round
+  bool ordered = false; // the group's samples are order[o0 .. o1) of the round's order list
+  bool hard = false;    // the predicted-hard part of a split group
+  int o0 = 0, o1 = 0;
   double t[kMaxTeam + 1];  // device seconds per sample with a team of G workgroups (G = 1 .. gmax)
   int lanes;            // teams
   int G;                // workgroups per team
@@ -750,10 +762,12 @@ void team_times(const stm_ctx* c, int l, int gmax, double* t) {
 // that needs the fewest workgroups -- a team of G runs floor(T / t(G))
 // samples in sequence (each warm-started from the previous) -- and the
 // workgroups of all groups fit the co-resident budget.
+int group_count(const Group& g) { return g.ordered ? g.o1 - g.o0 : g.n1 - g.n0; }
+
 bool fit_lanes(std::vector<Group>& gs, double T, int budget) {
   long used = 0;
   for (auto& g : gs) {
-    const int N = g.n1 - g.n0;
+    const int N = group_count(g);
     g.lanes = 0;
     g.G = 1;
     if (N <= 0) continue;
@@ -777,11 +791,11 @@ bool fit_lanes(std::vector<Group>& gs, double T, int budget) {
 void allocate_lanes(std::vector<Group>& gs, int budget) {
   double lo = 0.0, hi = 0.0;
   for (auto& g : gs) {
-    if (g.n1 <= g.n0) continue;
+    if (group_count(g) <= 0) continue;
     double tmin = g.t[1];
     for (int G = 2; G <= g.gmax; ++G) tmin = std::min(tmin, g.t[G]);
     lo = std::max(lo, tmin);
-    hi += (g.n1 - g.n0) * g.t[1];
+    hi += group_count(g) * g.t[1];
   }
   if (hi <= 0.0) {
     for (auto& g : gs) {
@@ -794,7 +808,7 @@ void allocate_lanes(std::vector<Group>& gs, int budget) {
   if (!fit_lanes(gs, hi, budget)) {  // budget too small for any balance: one workgroup per group
     for (auto& g : gs) {
       g.G = 1;
-      g.lanes = (g.n1 > g.n0) ? 1 : 0;
+      g.lanes = (group_count(g) > 0) ? 1 : 0;
     }
     return;
   }
@@ -924,6 +938,47 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         gs.push_back(g);
       }
     }
+    // Solve times within the finest level's fine member vary with the field:
+    // samples whose conductivity has the smallest minimum need the most
+    // Krylov iterations, and with one sample per team the slowest decides the
+    // launch.  The eighth with the smallest minimum becomes a group of its
+    // own, priced at hard_ratio times the others (the ratio of its slowest
+    // sample, measured), so that the allocation can give it larger teams.
+    std::vector<int> order;
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+      const int N = gs[gi].n1 - gs[gi].n0;
+      if (gs[gi].coarse || gs[gi].mlmc_level != L1 - 1 || N < 8 || gs[gi].gmax < 2) continue;
+      const int ef = c->levels[gs[gi].grid].dev.g[0].ne;
+      if ((st = grow(c, &c->d_rowmin, &c->rowmin_cap, (size_t)N * sizeof(double)))) return st;
+      hipError_t e = launch_row_min(S0 + off_sf[gs[gi].mlmc_level] + (size_t)gs[gi].n0 * ef, N, ef, c->d_rowmin,
+                                    c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "row min launch");
+      std::vector<double> mins(N);
+      STM_HIP(c, hipMemcpyAsync(mins.data(), c->d_rowmin, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      STM_HIP(c, hipStreamSynchronize(c->stream));
+      std::vector<int> idx(N);
+      for (int i = 0; i < N; ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return mins[a] < mins[b]; });
+      const int k = std::max(1, N / 8);
+      const int base = (int)order.size();
+      for (int i = 0; i < N; ++i) order.push_back(gs[gi].n0 + idx[i]);
+      Group h = gs[gi];
+      h.ordered = true;
+      h.hard = true;
+      h.o0 = base;
+      h.o1 = base + k;
+      for (int G = 1; G <= h.gmax; ++G) h.t[G] = gs[gi].t[G] * c->hard_ratio[gs[gi].grid];
+      gs[gi].ordered = true;
+      gs[gi].o0 = base + k;
+      gs[gi].o1 = base + N;
+      gs.push_back(h);
+      break;
+    }
+    if (!order.empty()) {
+      if ((st = grow(c, &c->d_order, &c->order_cap, order.size() * sizeof(int)))) return st;
+      STM_HIP(c, hipMemcpyAsync(c->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice,
+                                c->stream));
+    }
     int block = 256;
     for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
     allocate_lanes(gs, std::min(lane_budget, block_capacity(c, block)));
@@ -935,12 +990,13 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
     for (auto& g : gs) {
       const LevelHost& LH = c->levels[g.grid];
       const int l = g.mlmc_level;
-      const int N = g.n1 - g.n0;
+      const int N = group_count(g);
       for (int i = 0; i < g.lanes; ++i) {
         TeamTask t{};
         t.G = g.G;
         t.level = g.grid;
-        t.first = g.n0 + i;
+        t.order = g.ordered ? c->d_order : nullptr;
+        t.first = (g.ordered ? g.o0 : g.n0) + i;
         t.stride = g.lanes;
         t.count = (N - i + g.lanes - 1) / g.lanes;
         t.sigma = S0 + (g.coarse ? off_sc[l] : off_sf[l]);
@@ -960,11 +1016,38 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       std::vector<SampleStatsDev> tmp(nst);
       STM_HIP(c, hipMemcpy(tmp.data(), c->d_stats, nst * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
       std::vector<double> acc(L1 * (kMaxTeam + 1), 0.0), cnt(L1 * (kMaxTeam + 1), 0.0);
-      for (auto& g : gs) {
+      auto sample_of = [&](const Group& g, int j) { return g.ordered ? order[g.o0 + j] : g.n0 + j; };
+      auto mean_seconds = [&](const Group& g) {
         const size_t base = g.coarse ? off_stc[g.mlmc_level] : off_stf[g.mlmc_level];
-        for (int i = g.n0; i < g.n1; ++i) {
-          acc[g.grid * (kMaxTeam + 1) + g.G] += tmp[base + i].ticks * 1e-8;
+        double s = 0.0;
+        for (int j = 0; j < group_count(g); ++j) s += tmp[base + sample_of(g, j)].ticks * 1e-8;
+        return s / std::max(1, group_count(g));
+      };
+      for (auto& g : gs) {
+        if (g.hard) continue;  // the hard part informs hard_ratio, not the grid's table
+        const size_t base = g.coarse ? off_stc[g.mlmc_level] : off_stf[g.mlmc_level];
+        for (int j = 0; j < group_count(g); ++j) {
+          acc[g.grid * (kMaxTeam + 1) + g.G] += tmp[base + sample_of(g, j)].ticks * 1e-8;
           cnt[g.grid * (kMaxTeam + 1) + g.G] += 1.0;
+        }
+      }
+      // hard_ratio: the slowest hard sample (it decides when its team ends)
+      // and the normal part's mean, each relative to the model of the normal
+      // samples at the team size it ran with
+      auto max_seconds = [&](const Group& g) {
+        const size_t base = g.coarse ? off_stc[g.mlmc_level] : off_stf[g.mlmc_level];
+        double s = 0.0;
+        for (int j = 0; j < group_count(g); ++j) s = std::max(s, tmp[base + sample_of(g, j)].ticks * 1e-8);
+        return s;
+      };
+      for (auto& h : gs) {
+        if (!h.hard || h.lanes == 0 || group_count(h) == 0) continue;
+        for (auto& g : gs) {
+          if (g.hard || !g.ordered || g.grid != h.grid || g.mlmc_level != h.mlmc_level || g.coarse != h.coarse) continue;
+          if (g.lanes == 0 || group_count(g) == 0) break;
+          const double rh = max_seconds(h) / g.t[h.G], rn = mean_seconds(g) / g.t[g.G];
+          if (rh > 0 && rn > 0) c->hard_ratio[h.grid] = std::min(3.0, std::max(1.0, rh / rn));
+          break;
         }
       }
       for (int l = 0; l < L1; ++l)

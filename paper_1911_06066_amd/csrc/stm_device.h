@@ -94,6 +94,7 @@ constexpr int kFibStride = 3;
 struct TeamTask {
   int level;                 // index into the LevelDev table of the launch
   int first, stride, count;
+  const int* order;          // null: sample first + i stride; else sample order[first + i stride]
   const double* sigma;       // [*][ne0]
   double* u_out;             // [*][m][n0] or null (use the team buffer)
   const double* u_guess;     // [*][m][n0] or null

@@ -60,5 +60,7 @@ struct StatsLevelArgs {
 hipError_t launch_level_stats(const StatsLevelArgs& a, hipStream_t st);
 hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_fill_u32(unsigned* p, unsigned v, int64_t n, hipStream_t st);
+// out[s] = min over the E entries of row s of a[S][E] (device)
+hipError_t launch_row_min(const double* a, int S, int E, double* out, hipStream_t st);
 
 }  // namespace stm

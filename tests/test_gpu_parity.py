@@ -310,3 +310,26 @@ def test_mlmc_estimate_matches_oracle(torch_dev, precision):
     lm = out["level_mean"].cpu().numpy()
     for l in range(3):
         assert np.abs(lm[l] - ref["level_mean"][l]).max() <= (1e-9 if precision == "fp64" else 1e-6) * T
+
+
+def test_mlmc_with_split_finest_group_matches_oracle(torch_dev):
+    """With at least 8 pairs on the finest level, its fine members are split
+    by predicted cost into two groups solved through a sample order list;
+    the estimate still matches the oracle's statistics sample by sample."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[(9, 9), (17, 17)], steps=[8, 16], n_modes=8)
+    N = [10, 12]
+    basis = oapi.kl_basis(wl)
+    modes = [oapi.kl_modes(wl, l, basis) for l in range(2)]
+    xi = [stinputs.xi(wl["name"], l, N[l], wl["n_modes"]) for l in range(2)]
+    ctx = Context(wl)
+    for _ in range(2):  # the second call prices the hard part from the first call's measurement
+        out = ctx.mlmc_estimate(N, [torch.from_numpy(m).to(dev) for m in modes],
+                                [torch.from_numpy(x).to(dev) for x in xi])
+    ref = oapi.mlmc_estimate(wl, N, xi, modes, solve_mode="timestep")
+    T = wl["T"]
+    assert np.abs(out["mean"].cpu().numpy() - ref["mean"]).max() <= 1e-9 * T
+    assert np.abs(out["var"].cpu().numpy() - ref["var"]).max() <= 1e-9 * max(np.abs(ref["var"]).max(), 1e-12)
+    np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8, atol=1e-15)
+    assert out["N"] == N and out["worst_status"] == 0
