@@ -173,7 +173,8 @@ def compare_paths(wl, N, modes, xi, fp64_value, fp64_out):
     wlm = dict(wl, precision="mixed")
     tun = autotune.level_tuning(wl, "mixed")
     ctx = Context(wlm, **({"level_tuning": tun} if tun else {}))
-    mo = ctx.mlmc_estimate(N, modes, xi)
+    for _ in range(2):  # warm-up, as for the main measurement: the schedule settles after two
+        mo = ctx.mlmc_estimate(N, modes, xi)
     torch.cuda.synchronize()
 
     def rel(a, b):
