@@ -64,6 +64,9 @@ struct stm_ctx {
   // device seconds of the predicted-hard samples of a grid relative to the
   // others at the same team size (measured after every launch that splits)
   double hard_ratio[STM_MAX_LEVELS] = {1.3, 1.3, 1.3, 1.3, 1.3, 1.3, 1.3, 1.3};
+  // slowest over mean device seconds of the rest of a split group, which also
+  // runs one sample per team, so that its slowest sample decides its end too
+  double tail_ratio[STM_MAX_LEVELS] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
   int stage_bytes = 48 * 1024;   // dynamic LDS per solver workgroup
 };
 
@@ -943,7 +946,8 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
     // Krylov iterations, and with one sample per team the slowest decides the
     // launch.  The eighth with the smallest minimum becomes a group of its
     // own, priced at hard_ratio times the others (the ratio of its slowest
-    // sample, measured), so that the allocation can give it larger teams.
+    // sample, measured), so that the allocation can give it larger teams; the
+    // others are priced at their own measured slowest-to-mean tail_ratio.
     std::vector<int> order;
     for (size_t gi = 0; gi < gs.size(); ++gi) {
       const int N = gs[gi].n1 - gs[gi].n0;
@@ -968,6 +972,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
       h.o0 = base;
       h.o1 = base + k;
       for (int G = 1; G <= h.gmax; ++G) h.t[G] = gs[gi].t[G] * c->hard_ratio[gs[gi].grid];
+      for (int G = 1; G <= gs[gi].gmax; ++G) gs[gi].t[G] *= c->tail_ratio[gs[gi].grid];
       gs[gi].ordered = true;
       gs[gi].o0 = base + k;
       gs[gi].o1 = base + N;
@@ -1045,8 +1050,12 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         for (auto& g : gs) {
           if (g.hard || !g.ordered || g.grid != h.grid || g.mlmc_level != h.mlmc_level || g.coarse != h.coarse) continue;
           if (g.lanes == 0 || group_count(g) == 0) break;
-          const double rh = max_seconds(h) / g.t[h.G], rn = mean_seconds(g) / g.t[g.G];
+          // g.t carries this launch's tail factor: divide it out to compare with the mean model
+          const double tail = c->tail_ratio[g.grid];
+          const double rh = max_seconds(h) / (g.t[h.G] / tail), rn = mean_seconds(g) / (g.t[g.G] / tail);
           if (rh > 0 && rn > 0) c->hard_ratio[h.grid] = std::min(3.0, std::max(1.0, rh / rn));
+          const double mn = mean_seconds(g);
+          if (mn > 0) c->tail_ratio[g.grid] = std::min(2.0, std::max(1.0, max_seconds(g) / mn));
           break;
         }
       }
