@@ -88,7 +88,7 @@ def tune(wl, precision=None, samples=32, candidates=CANDIDATES, seed=4242, block
         # seconds per sample against team size, with the chosen smoother
         team = [0.0] * MAX_TEAM
         if best:
-            gmax = max(1, min(MAX_TEAM, int(wl["levels"][l][1]) // 4))
+            gmax = max(1, min(MAX_TEAM, int(wl["levels"][l][1]) // 3))
             tune_l = [None] * len(wl["levels"])
             tune_l[l] = (best["smooth_sweeps"], best["cheb_ratio"])
             for G in TEAM_SIZES:

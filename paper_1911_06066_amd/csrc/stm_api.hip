@@ -452,12 +452,12 @@ stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
   return STM_OK;
 }
 
-// Largest team size a level allows: single-grid V-cycle and >= 4 node rows per member
+// Largest team size a level allows: single-grid V-cycle and >= 3 node rows per member
 // (a member's staged tiles carry one halo row on each side).
 int max_team(const stm_ctx* c, int level) {
   const LevelDev& d = c->levels[level].dev;
   if (d.nmg > 1) return 1;
-  return std::max(1, std::min(kMaxTeam, d.g[0].ny / 4));
+  return std::max(1, std::min(kMaxTeam, d.g[0].ny / 3));
 }
 
 // Workgroups that can be resident at once for the solver configuration.
