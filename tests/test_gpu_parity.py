@@ -312,13 +312,14 @@ def test_mlmc_estimate_matches_oracle(torch_dev, precision):
         assert np.abs(lm[l] - ref["level_mean"][l]).max() <= (1e-9 if precision == "fp64" else 1e-6) * T
 
 
-def test_mlmc_with_split_finest_group_matches_oracle(torch_dev):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mlmc_with_split_finest_group_matches_oracle(torch_dev, precision):
     """With at least 8 pairs on the finest level, its fine members are split
     by predicted cost into two groups solved through a sample order list;
     the estimate still matches the oracle's statistics sample by sample."""
     torch, dev = torch_dev
     from paper_1911_06066_amd import Context
-    wl = _wl(levels=[(9, 9), (17, 17)], steps=[8, 16], n_modes=8)
+    wl = _wl(levels=[(9, 9), (17, 17)], steps=[8, 16], n_modes=8, precision=precision)
     N = [10, 12]
     basis = oapi.kl_basis(wl)
     modes = [oapi.kl_modes(wl, l, basis) for l in range(2)]
@@ -329,7 +330,11 @@ def test_mlmc_with_split_finest_group_matches_oracle(torch_dev):
                                 [torch.from_numpy(x).to(dev) for x in xi])
     ref = oapi.mlmc_estimate(wl, N, xi, modes, solve_mode="timestep")
     T = wl["T"]
-    assert np.abs(out["mean"].cpu().numpy() - ref["mean"]).max() <= 1e-9 * T
-    assert np.abs(out["var"].cpu().numpy() - ref["var"]).max() <= 1e-9 * max(np.abs(ref["var"]).max(), 1e-12)
-    np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8, atol=1e-15)
+    if precision == "fp64":
+        assert np.abs(out["mean"].cpu().numpy() - ref["mean"]).max() <= 1e-9 * T
+        assert np.abs(out["var"].cpu().numpy() - ref["var"]).max() <= 1e-9 * max(np.abs(ref["var"]).max(), 1e-12)
+        np.testing.assert_allclose(out["V"], ref["V"], rtol=1e-8, atol=1e-15)
+    else:
+        assert np.abs(out["mean"].cpu().numpy() - ref["mean"]).max() <= 1e-6 * T
+        assert np.linalg.norm(out["var"].cpu().numpy() - ref["var"]) <= 1e-4 * np.linalg.norm(ref["var"])
     assert out["N"] == N and out["worst_status"] == 0

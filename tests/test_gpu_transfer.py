@@ -69,7 +69,22 @@ def test_prolonged_coarse_solution_as_first_iterate(torch_dev, workload):
     assert _rel(u2.cpu().numpy(), u1.cpu().numpy()) < 1e-9
 
 
-@pytest.mark.parametrize("case", ["2d", "strip"])
+def test_prolongation_rejects_bad_arguments(torch_dev):
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context, StmError
+    wl = stinputs.workload("small_mc_2d", levels=[(9, 9), (17, 17)], steps=[4, 8])
+    ctx = Context(wl)
+    nc, _, mc = ctx.sizes[0]
+    u = torch.zeros((2, mc, nc), dtype=torch.float64, device=dev)
+    out = torch.empty((2, 8, ctx.sizes[1][0]), dtype=torch.float64, device=dev)
+    for level in (0, 2):
+        st = ctx.lib.stm_prolong_st(ctx.h, level, u.data_ptr(), 2, out.data_ptr())
+        assert st == -1
+    assert ctx.lib.stm_prolong_st(ctx.h, 1, None, 2, out.data_ptr()) == -1
+    assert ctx.lib.stm_prolong_st(ctx.h, 1, u.data_ptr(), 0, out.data_ptr()) == 0
+
+
+@pytest.mark.parametrize("case", ["2d", "strip", "strip_split"])
 def test_space_time_qoi_mlmc_matches_oracle(torch_dev, case):
     """E[u] on the finest space-time grid (Sec. 4.1): mean, variance, level
     fields and V_l in the L^2(0, T; L^2(D)) sense against the oracle."""
@@ -82,7 +97,7 @@ def test_space_time_qoi_mlmc_matches_oracle(torch_dev, case):
     else:
         wl = stinputs.workload("cable1d", levels=[(32, 2), (63, 2), (125, 2)], steps=[4, 8, 16],
                                kl_grid=(125, 2))
-        N = [16, 8, 4]
+        N = [16, 8, 4] if case == "strip" else [16, 8, 9]  # 9 finest pairs: the split group path
     basis = oapi.kl_basis(wl)
     modes = [oapi.kl_modes(wl, l, basis) for l in range(3)]
     xi = [stinputs.xi(wl["name"], l, N[l], wl["n_modes"]) for l in range(3)]
