@@ -550,6 +550,168 @@ struct Team {
     __syncthreads();
   }
 
+  // Two Jacobi sweeps on grid 0 in one pass over the tiles (2D):
+  // out = J2(J1(x)), Jq(v) = v + omq (b - A v) dinv.  A tile stages x, the
+  // mass weights, b and dinv over its rows plus two halo rows each side,
+  // computes the first sweep on its rows plus one row each side into LDS, and
+  // the second sweep on its rows from there.  Halo rows of the first sweep take
+  // the same operations in the same order as in the pass that owns them, so the
+  // result equals two single sweeps.  out must not alias x.  Ends with a team
+  // barrier.
+  __device__ void jacobi_pair(const TI* __restrict__ x, const TI* __restrict__ b, TI* __restrict__ out, TI om1,
+                              TI om2) const {
+    static_assert(DIM == 2, "the fused sweep pair is 2D");
+    using T = TI;
+    constexpr int NV = 4;
+    constexpr int U = 4;
+    constexpr int UA = 2;
+    const GridDev& g = L->g[0];
+    bytes = uni(bytes + (5.0 * sizeof(TI) * g.n + dbytes(0)));
+    const T* __restrict__ w = mgW(0);
+    const T* __restrict__ di = dinv;
+    const int nx = g.nx, EX = g.ex;
+    const unsigned mnx = g.mnx, mex = g.mex;
+    const int Ry = sizeof(T) == 8 ? L->tile_p8 : L->tile_p4;
+    const double* __restrict__ sg = sigma;
+    const double* __restrict__ fib = L->fib;
+    const double tau = prm.tau, zr = prm.zr;
+    const T hx = T(g.hx), hy = T(g.hy);
+    const T cxx = hy / (T(6) * hx), cyy = hx / (T(6) * hy), cm = hx * hy / T(36);
+    const T th = T(prm.theta);
+    for (int j0 = jb0; j0 < jb1; j0 += Ry) {
+      const int je = min(j0 + Ry, jb1);                          // second sweep: rows [j0, je)
+      const int a0 = max(j0 - 1, 0), a1 = min(je + 1, g.ny);     // first sweep: rows [a0, a1)
+      const int jr0 = max(j0 - 2, 0), jr1 = min(je + 1, g.ny - 1);  // staged node rows [jr0, jr1]
+      const int ey0 = jr0, ey1 = min(je, g.ey - 1);              // staged element rows [ey0, ey1]
+      const int nst = (jr1 - jr0 + 1) * nx;
+      const int nse = (ey1 - ey0 + 1) * EX;
+      T* lx0 = reinterpret_cast<T*>(smem);
+      T* lw = lx0 + nst;
+      T* lb = lw + nst;
+      T* ld = lb + nst;
+      T* lx1 = ld + nst;
+      double* ls = reinterpret_cast<double*>(smem + ((5 * (size_t)nst * sizeof(T) + 15) & ~(size_t)15));
+      T* lc = reinterpret_cast<T*>(ls + nse);  // [NV][nse]
+      double* lf = reinterpret_cast<double*>(
+          reinterpret_cast<unsigned char*>(lc) + ((NV * (size_t)nse * sizeof(T) + 15) & ~(size_t)15));
+      // ---- stage ----
+      const int gq0 = jr0 * nx;
+      for (int qb = threadIdx.x; qb < nst; qb += BLOCK * U) {
+        T r0[U], r1[U], r2[U], r3[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = qb + u * BLOCK;
+          if (q < nst) {
+            r0[u] = x[gq0 + q];
+            r1[u] = w[gq0 + q];
+            r2[u] = b[gq0 + q];
+            r3[u] = di[gq0 + q];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = qb + u * BLOCK;
+          if (q < nst) {
+            lx0[q] = r0[u];
+            lw[q] = r1[u];
+            lb[q] = r2[u];
+            ld[q] = r3[u];
+          }
+        }
+      }
+      {
+        const int ge0 = ey0 * EX;
+        for (int qb = threadIdx.x; qb < nse; qb += BLOCK * U) {
+          double rs[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nse) rs[u] = sg[ge0 + q];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int q = qb + u * BLOCK;
+            if (q < nse) ls[q] = rs[u];
+          }
+        }
+        for (int q = threadIdx.x; q < kFibStride * (ey1 - ey0 + 1); q += BLOCK) lf[q] = fib[kFibStride * ey0 + q];
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int sweep = 0; sweep < 2; ++sweep) {
+        // element rows [e0, e1] whose contributions this sweep gathers
+        const int e0 = sweep == 0 ? ey0 : max(j0 - 1, 0);
+        const int e1 = sweep == 0 ? ey1 : min(je - 1, g.ey - 1);
+        const T* __restrict__ lxs = sweep == 0 ? lx0 : lx1;
+        const int ne = (e1 - e0 + 1) * EX;
+        // ---- phase A: element contributions of M (w v) + K (theta v) ----
+        for (int qb = threadIdx.x; qb < ne; qb += UA * BLOCK) {
+          T kv[UA][NV], mv[UA][NV], o4[UA][NV];
+          Tensor2<T> D[UA];
+          int qs[UA];
+#pragma unroll
+          for (int h = 0; h < UA; ++h) {
+            const int q = qb + h * BLOCK;
+            const int qq = q < ne ? q : 0;
+            const int r = fdiv(qq, mex);
+            const int ex = qq - r * EX;
+            const int rr = e0 - ey0 + r;  // staged element row
+            qs[h] = rr * EX + ex;
+            D[h] = tensor_from<T, 2>(ls[qs[h]], lf + kFibStride * rr, tau, zr);
+            const int base = rr * nx + ex;  // staged node rows start at ey0
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const int o = base + ((v >> 1) & 1) * nx + (v & 1);
+              const T a = lxs[o], ww = lw[o];
+              kv[h][v] = th * a;
+              mv[h][v] = ww * a;
+            }
+          }
+#pragma unroll
+          for (int h = 0; h < UA; ++h) elem_apply_2d<T>(kv[h], mv[h], D[h], cxx, cyy, cm, o4[h]);
+#pragma unroll
+          for (int h = 0; h < UA; ++h) {
+            if (qb + h * BLOCK < ne) {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) lc[v * nse + qs[h]] = o4[h][v];
+            }
+          }
+        }
+        __syncthreads();
+        // ---- phase B: nodes of rows [n0r, n1r) ----
+        const int n0r = sweep == 0 ? a0 : j0, n1r = sweep == 0 ? a1 : je;
+        const int nc = (n1r - n0r) * nx;
+        const T om = sweep == 0 ? om1 : om2;
+        for (int q = threadIdx.x; q < nc; q += BLOCK) {
+          const int r = fdiv(q, mnx);
+          const int i = q - r * nx;
+          const int j = n0r + r;
+          T y = T(0);
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb) {
+            const int ey = j - 1 + bb;
+            const bool oky = ey >= 0 && ey < g.ey;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const int ex = i - 1 + a;
+              const bool ok = oky && ex >= 0 && ex < EX;
+              const int el = (ey - ey0) * EX + ex;
+              const int v = (1 - a) + 2 * (1 - bb);
+              const T cv = lc[v * nse + (ok ? el : 0)];
+              y += ok ? cv : T(0);
+            }
+          }
+          const int o = (j - jr0) * nx + i;
+          const T xn = lxs[o] + om * (lb[o] - y) * ld[o];
+          if (sweep == 0) lx1[o] = xn;
+          else out[j * nx + i] = xn;
+        }
+        __syncthreads();
+      }
+    }
+    if (G > 1) team_barrier();
+  }
+
   __device__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
     const int n = L->g[l].n;
     bytes = uni(bytes + (4.0 * sizeof(TI) * n + dbytes(l)));
@@ -636,8 +798,22 @@ struct Team {
       // sweep s (1-based) of nc writes buf[(nc - s + 1) % 2]: the last one out0
       TI* buf[2] = {mgT(0), out0};
       const int nc = L->sweeps;
-      jacobi(0, b0, nullptr, buf[nc % 2], wgt(0, 0));
-      for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[(nc - s + 2) % 2], buf[(nc - s + 1) % 2], wgt(0, s - 1));
+      if constexpr (DIM == 3) {
+        // sweep s (1-based) of nc writes buf[(nc - s + 1) % 2]: the last one out0
+        jacobi(0, b0, nullptr, buf[nc % 2], wgt(0, 0));
+        for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[(nc - s + 2) % 2], buf[(nc - s + 1) % 2], wgt(0, s - 1));
+      } else {
+        // The sweeps after the first run as fused pairs (one pass each), and a
+        // single sweep when one is left.  Pass t (1-based) of P writes
+        // buf[(P - t + 1) % 2]: the last one out0.
+        const int np = (nc - 1) / 2;
+        const int P = nc - np;
+        jacobi(0, b0, nullptr, buf[P % 2], wgt(0, 0));
+        int s = 2, t = 2;
+        for (int q = 0; q < np; ++q, s += 2, ++t)
+          jacobi_pair(buf[(P - t + 2) % 2], b0, buf[(P - t + 1) % 2], wgt(0, s - 1), wgt(0, s));
+        for (; s <= nc; ++s, ++t) jacobi(0, b0, buf[(P - t + 2) % 2], buf[(P - t + 1) % 2], wgt(0, s - 1));
+      }
       return;
     }
     const int nmg = L->nmg;

@@ -338,6 +338,21 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
     if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
     if (es == 0) { d.tile_y8 = by; d.tile_z8 = bz; } else { d.tile_y4 = by; d.tile_z4 = bz; }
   }
+  // fused two-sweep smoother pass (2D): five nodal fields over the tile's rows
+  // plus two halo rows each side, element conductivities and contributions and
+  // fibre rows of the tile's rows plus three
+  for (int es = 0; es < 2 && p.dim == 2; ++es) {
+    const size_t fb = es == 0 ? 8 : 4;
+    int by = 0;
+    for (int ry = 1; ry <= g0.ny; ++ry) {
+      const size_t sy = std::min(ry + 4, g0.ny), sey = std::min(ry + 3, g0.ey);
+      const size_t bytes = 5 * fb * sy * g0.nx + 16 + (8 + 4 * fb) * sey * g0.ex + 16 + 8 * kFibStride * sey;
+      if (bytes > budget) break;
+      by = ry;
+    }
+    if (by == 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
+    if (es == 0) d.tile_p8 = by; else d.tile_p4 = by;
+  }
   out.u_bytes = (int64_t)align_up(8 * (size_t)n0 * lv.m);
   d.team_bytes = out.team_bytes;
   return STM_OK;

@@ -56,6 +56,9 @@ struct LevelDev {
   // LDS tiles of grid-0 stencil passes: node rows (y) and planes (z) per
   // tile, for 8-byte (index 0) and 4-byte (index 1) staged fields
   int tile_y8, tile_z8, tile_y4, tile_z4;
+  // node rows per tile of the fused two-sweep smoother pass (2D), for 8-byte
+  // and 4-byte inner vectors
+  int tile_p8, tile_p4;
 };
 
 // Physics and solver parameters (uniform across a launch).
