@@ -26,6 +26,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
 CANDIDATES = [(8, 10.0), (10, 10.0), (12, 10.0), (14, 10.0), (16, 10.0), (16, 20.0), (20, 10.0), (24, 10.0)]
+# 3D levels measured faster with wider Chebyshev intervals (ratio 20 against
+# 10 on the 65x65x17 slab), so their list spans ratios 10 to 30.
+CANDIDATES_3D = [(8, 10.0), (12, 10.0), (8, 20.0), (12, 20.0), (16, 20.0), (24, 20.0), (12, 30.0), (16, 30.0),
+                 (24, 30.0)]
 TEAM_SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16)
 MAX_TEAM = 16
 
@@ -38,11 +42,14 @@ def _level_key(wl, l):
     return {"grid": list(wl["levels"][l]), "steps": int(wl["steps"][l])}
 
 
-def tune(wl, precision=None, samples=32, candidates=CANDIDATES, seed=4242, block=0, log=print):
+def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, log=print):
     """Measure every candidate on every level; return the tuning record."""
     import torch
 
     from . import Context, klmodes
+
+    if candidates is None:
+        candidates = CANDIDATES_3D if wl.get("dim", 2) == 3 else CANDIDATES
 
     precision = precision or wl.get("precision", "fp64")
     dev = torch.device("cuda:0")
