@@ -712,6 +712,146 @@ struct Team {
     if (G > 1) team_barrier();
   }
 
+  // Every sweep of the smoother in one pass, for a one-workgroup team whose
+  // grid fits one tile (2D): the mass weights, b, dinv, sigma and the fibre
+  // rows are staged once; the first sweep (from x = 0) is om b dinv, the later
+  // ones alternate between two LDS vectors, and the last is written to out.
+  // Each sweep takes the operations of a single sweep in the same order.  Ends
+  // with a workgroup barrier.
+  __device__ void jacobi_resident(const TI* __restrict__ b, TI* __restrict__ out, int nc) const {
+    static_assert(DIM == 2, "the resident smoother is 2D");
+    using T = TI;
+    constexpr int NV = 4;
+    constexpr int U = 4;
+    constexpr int UA = 2;
+    const GridDev& g = L->g[0];
+    bytes = uni(bytes + (4.0 * sizeof(TI) * g.n + dbytes(0)));
+    const T* __restrict__ w = mgW(0);
+    const T* __restrict__ di = dinv;
+    const int nx = g.nx, EX = g.ex;
+    const unsigned mnx = g.mnx, mex = g.mex;
+    const double tau = prm.tau, zr = prm.zr;
+    const T hx = T(g.hx), hy = T(g.hy);
+    const T cxx = hy / (T(6) * hx), cyy = hx / (T(6) * hy), cm = hx * hy / T(36);
+    const T th = T(prm.theta);
+    const int nst = g.n, nse = g.ne;
+    T* lx0 = reinterpret_cast<T*>(smem);
+    T* lw = lx0 + nst;
+    T* lb = lw + nst;
+    T* ld = lb + nst;
+    T* lx1 = ld + nst;
+    double* ls = reinterpret_cast<double*>(smem + ((5 * (size_t)nst * sizeof(T) + 15) & ~(size_t)15));
+    T* lc = reinterpret_cast<T*>(ls + nse);  // [NV][nse]
+    double* lf = reinterpret_cast<double*>(
+        reinterpret_cast<unsigned char*>(lc) + ((NV * (size_t)nse * sizeof(T) + 15) & ~(size_t)15));
+    // ---- stage ----
+    for (int qb = threadIdx.x; qb < nst; qb += BLOCK * U) {
+      T r1[U], r2[U], r3[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qb + u * BLOCK;
+        if (q < nst) {
+          r1[u] = w[q];
+          r2[u] = b[q];
+          r3[u] = di[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qb + u * BLOCK;
+        if (q < nst) {
+          lw[q] = r1[u];
+          lb[q] = r2[u];
+          ld[q] = r3[u];
+        }
+      }
+    }
+    for (int qb = threadIdx.x; qb < nse; qb += BLOCK * U) {
+      double rs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qb + u * BLOCK;
+        if (q < nse) rs[u] = sigma[q];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = qb + u * BLOCK;
+        if (q < nse) ls[q] = rs[u];
+      }
+    }
+    for (int q = threadIdx.x; q < kFibStride * g.ey; q += BLOCK) lf[q] = L->fib[q];
+    __syncthreads();
+    // ---- sweep 1 from x = 0 ----
+    {
+      const T om = wgt(0, 0);
+      T* dst = nc == 1 ? out : lx0;
+      for (int q = threadIdx.x; q < nst; q += BLOCK) dst[q] = om * lb[q] * ld[q];
+      __syncthreads();
+    }
+#pragma unroll 1
+    for (int s = 2; s <= nc; ++s) {
+      const T* __restrict__ cur = (s % 2 == 0) ? lx0 : lx1;
+      T* nxt = (s % 2 == 0) ? lx1 : lx0;
+      // ---- phase A: element contributions of M (w v) + K (theta v) ----
+      for (int qb = threadIdx.x; qb < nse; qb += UA * BLOCK) {
+        T kv[UA][NV], mv[UA][NV], o4[UA][NV];
+        Tensor2<T> D[UA];
+#pragma unroll
+        for (int h = 0; h < UA; ++h) {
+          const int q = qb + h * BLOCK;
+          const int qq = q < nse ? q : 0;
+          const int r = fdiv(qq, mex);
+          const int ex = qq - r * EX;
+          D[h] = tensor_from<T, 2>(ls[qq], lf + kFibStride * r, tau, zr);
+          const int base = r * nx + ex;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int o = base + ((v >> 1) & 1) * nx + (v & 1);
+            const T a = cur[o], ww = lw[o];
+            kv[h][v] = th * a;
+            mv[h][v] = ww * a;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < UA; ++h) elem_apply_2d<T>(kv[h], mv[h], D[h], cxx, cyy, cm, o4[h]);
+#pragma unroll
+        for (int h = 0; h < UA; ++h) {
+          const int q = qb + h * BLOCK;
+          if (q < nse) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) lc[v * nse + q] = o4[h][v];
+          }
+        }
+      }
+      __syncthreads();
+      // ---- phase B: every node ----
+      const T om = wgt(0, s - 1);
+      for (int q = threadIdx.x; q < nst; q += BLOCK) {
+        const int j = fdiv(q, mnx);
+        const int i = q - j * nx;
+        T y = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+          const int ey = j - 1 + bb;
+          const bool oky = ey >= 0 && ey < g.ey;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int ex = i - 1 + a;
+            const bool ok = oky && ex >= 0 && ex < EX;
+            const int el = ey * EX + ex;
+            const int v = (1 - a) + 2 * (1 - bb);
+            const T cv = lc[v * nse + (ok ? el : 0)];
+            y += ok ? cv : T(0);
+          }
+        }
+        const T xn = cur[q] + om * (lb[q] - y) * ld[q];
+        if (s == nc) out[q] = xn;
+        else nxt[q] = xn;
+      }
+      __syncthreads();
+    }
+  }
+
   __device__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
     const int n = L->g[l].n;
     bytes = uni(bytes + (4.0 * sizeof(TI) * n + dbytes(l)));
@@ -803,9 +943,14 @@ struct Team {
         jacobi(0, b0, nullptr, buf[nc % 2], wgt(0, 0));
         for (int s = 2; s <= nc; ++s) jacobi(0, b0, buf[(nc - s + 2) % 2], buf[(nc - s + 1) % 2], wgt(0, s - 1));
       } else {
-        // The sweeps after the first run as fused pairs (one pass each), and a
-        // single sweep when one is left.  Pass t (1-based) of P writes
-        // buf[(P - t + 1) % 2]: the last one out0.
+        // A one-workgroup team whose grid fits one tile runs every sweep in one
+        // pass.  Otherwise the sweeps after the first run as fused pairs (one
+        // pass each), and a single sweep when one is left.  Pass t (1-based) of
+        // P writes buf[(P - t + 1) % 2]: the last one out0.
+        if (G == 1 && (sizeof(TI) == 8 ? L->tile_p8 : L->tile_p4) >= L->g[0].ny) {
+          jacobi_resident(b0, out0, nc);
+          return;
+        }
         const int np = (nc - 1) / 2;
         const int P = nc - np;
         jacobi(0, b0, nullptr, buf[P % 2], wgt(0, 0));

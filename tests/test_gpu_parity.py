@@ -109,6 +109,28 @@ def test_odd_and_single_sweep_counts_match_oracle(torch_dev, sweeps):
     assert _rel(u.cpu().numpy(), U_ref) < 1e-9
 
 
+@pytest.mark.parametrize("precision,sweeps", [("fp64", 1), ("fp64", 2), ("fp64", 14), ("mixed", 9)])
+def test_resident_smoother_matches_oracle(torch_dev, precision, sweeps):
+    """One workgroup per sample on a grid that fits one tile: every sweep of
+    the smoother runs in LDS within one pass."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[(33, 33)], steps=[24], precision=precision)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl, level_tuning=[(sweeps, 10.0)], team_size=1)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    assert ctx.timings()["solve_blocks"] == 2
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    if precision == "fp64":
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+    else:
+        t, _ = ctx.activation_map(0, u)
+        t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-6 * wl["T"]
+
+
 @pytest.mark.parametrize("precision,G", [("fp64", 1), ("fp64", 3), ("mixed", 1), ("mixed", 3)])
 def test_fused_sweep_pairs_on_small_tiles_match_oracle(torch_dev, precision, G):
     """In 2D the smoother runs its sweeps in fused pairs, each tile with a
