@@ -556,17 +556,18 @@ struct Team {
   // computes the first sweep on its rows plus one row each side into LDS, and
   // the second sweep on its rows from there.  Halo rows of the first sweep take
   // the same operations in the same order as in the pass that owns them, so the
-  // result equals two single sweeps.  out must not alias x.  Ends with a team
-  // barrier.
-  __device__ void jacobi_pair(const TI* __restrict__ x, const TI* __restrict__ b, TI* __restrict__ out, TI om1,
-                              TI om2) const {
+  // result equals two single sweeps.  x == null stands for the sweep from zero,
+  // x = om0 b dinv, formed while staging (three sweeps in the pass).  out must
+  // not alias x.  Ends with a team barrier.
+  __device__ void jacobi_pair(const TI* __restrict__ x, const TI* __restrict__ b, TI* __restrict__ out, TI om0,
+                              TI om1, TI om2) const {
     static_assert(DIM == 2, "the fused sweep pair is 2D");
     using T = TI;
     constexpr int NV = 4;
     constexpr int U = 4;
     constexpr int UA = 2;
     const GridDev& g = L->g[0];
-    bytes = uni(bytes + (5.0 * sizeof(TI) * g.n + dbytes(0)));
+    bytes = uni(bytes + ((x ? 5.0 : 4.0) * sizeof(TI) * g.n + dbytes(0)));
     const T* __restrict__ w = mgW(0);
     const T* __restrict__ di = dinv;
     const int nx = g.nx, EX = g.ex;
@@ -602,7 +603,7 @@ struct Team {
         for (int u = 0; u < U; ++u) {
           const int q = qb + u * BLOCK;
           if (q < nst) {
-            r0[u] = x[gq0 + q];
+            if (x) r0[u] = x[gq0 + q];
             r1[u] = w[gq0 + q];
             r2[u] = b[gq0 + q];
             r3[u] = di[gq0 + q];
@@ -612,7 +613,7 @@ struct Team {
         for (int u = 0; u < U; ++u) {
           const int q = qb + u * BLOCK;
           if (q < nst) {
-            lx0[q] = r0[u];
+            lx0[q] = x ? r0[u] : om0 * r2[u] * r3[u];
             lw[q] = r1[u];
             lb[q] = r2[u];
             ld[q] = r3[u];
@@ -951,12 +952,21 @@ struct Team {
           jacobi_resident(b0, out0, nc);
           return;
         }
+        // With three or more sweeps the first pass runs sweeps 1 to 3 (the sweep
+        // from zero formed while staging).
         const int np = (nc - 1) / 2;
-        const int P = nc - np;
-        jacobi(0, b0, nullptr, buf[P % 2], wgt(0, 0));
-        int s = 2, t = 2;
-        for (int q = 0; q < np; ++q, s += 2, ++t)
-          jacobi_pair(buf[(P - t + 2) % 2], b0, buf[(P - t + 1) % 2], wgt(0, s - 1), wgt(0, s));
+        const int P = nc - np - (nc >= 3 ? 1 : 0);
+        int s, t;
+        if (nc >= 3) {
+          jacobi_pair(nullptr, b0, buf[P % 2], wgt(0, 0), wgt(0, 1), wgt(0, 2));
+          s = 4;
+        } else {
+          jacobi(0, b0, nullptr, buf[P % 2], wgt(0, 0));
+          s = 2;
+        }
+        t = 2;
+        for (; s + 1 <= nc; s += 2, ++t)
+          jacobi_pair(buf[(P - t + 2) % 2], b0, buf[(P - t + 1) % 2], TI(0), wgt(0, s - 1), wgt(0, s));
         for (; s <= nc; ++s, ++t) jacobi(0, b0, buf[(P - t + 2) % 2], buf[(P - t + 1) % 2], wgt(0, s - 1));
       }
       return;
