@@ -272,8 +272,9 @@ struct Team {
     const GridDev& g = L->g[0];
     const int nx = g.nx, EX = g.ex;
     const unsigned mnx = g.mnx, mex = g.mex;
-    const int Ry = sizeof(T) == 8 ? L->tile_y8 : L->tile_y4;
-    const int Rz = (DIM == 3) ? (sizeof(T) == 8 ? L->tile_z8 : L->tile_z4) : 1;
+    const int nf = 2 + (f2 ? 1 : 0) + (f3 ? 1 : 0);
+    const int Ry = L->tile_y[sizeof(T) == 8 ? 0 : 1][nf - 2];
+    const int Rz = (DIM == 3) ? L->tile_z[sizeof(T) == 8 ? 0 : 1][nf - 2] : 1;
     const int nzz = (DIM == 3) ? g.nz : 1;
     const double* __restrict__ sg = sigma;
     const double* __restrict__ fib = L->fib;
@@ -283,7 +284,6 @@ struct Team {
     const T cyy = (DIM == 3) ? hx * hz / (T(36) * hy) : hx / (T(6) * hy);
     const T czz = hx * hy / (T(36) * hz), cxy = hz / T(24);
     const T cm = (DIM == 3) ? hx * hy * hz / T(216) : hx * hy / T(36);
-    const int nf = 2 + (f2 ? 1 : 0) + (f3 ? 1 : 0);
     for (int k0 = 0; k0 < nzz; k0 += Rz) {
       for (int j0 = jb0; j0 < jb1; j0 += Ry) {
         const int je = min(j0 + Ry, jb1);  // computed rows [j0, je)

@@ -310,33 +310,37 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   }
   out.team_bytes = (int64_t)off;
   d.off_U = off;
-  // LDS tiles: maximise interior / staged nodes within the staging budget
+  // LDS tiles: maximise interior / staged nodes within the staging budget,
+  // per field size and number of staged nodal fields (2 to 4)
   const size_t budget = (size_t)c->stage_bytes;
   for (int es = 0; es < 2; ++es) {
     const size_t fb = es == 0 ? 8 : 4;
-    int by = 1, bz = 1;
-    double best = -1.0;
-    const int zmax = p.dim == 3 ? g0.nz : 1;
-    for (int rz = 1; rz <= zmax; ++rz) {
-      for (int ry = 1; ry <= g0.ny; ++ry) {
-        const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
-        const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
-        const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
-        // four staged nodal fields, element conductivities, element
-        // contributions, fibre rows of the tile
-        const size_t bytes = 4 * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex + 16 +
-                             8 * kFibStride * (size_t)(p.dim == 2 ? ey : ez);
-        if (bytes > budget) break;
-        const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
-        if (eff > best) {
-          best = eff;
-          by = ry;
-          bz = rz;
+    for (int nfl = 2; nfl <= 4; ++nfl) {
+      int by = 1, bz = 1;
+      double best = -1.0;
+      const int zmax = p.dim == 3 ? g0.nz : 1;
+      for (int rz = 1; rz <= zmax; ++rz) {
+        for (int ry = 1; ry <= g0.ny; ++ry) {
+          const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
+          const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
+          const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
+          // staged nodal fields, element conductivities, element
+          // contributions, fibre rows of the tile
+          const size_t bytes = nfl * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex +
+                               16 + 8 * kFibStride * (size_t)(p.dim == 2 ? ey : ez);
+          if (bytes > budget) break;
+          const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
+          if (eff > best) {
+            best = eff;
+            by = ry;
+            bz = rz;
+          }
         }
       }
+      if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
+      d.tile_y[es][nfl - 2] = by;
+      d.tile_z[es][nfl - 2] = bz;
     }
-    if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
-    if (es == 0) { d.tile_y8 = by; d.tile_z8 = bz; } else { d.tile_y4 = by; d.tile_z4 = bz; }
   }
   // fused two-sweep smoother pass (2D): five nodal fields over the tile's rows
   // plus two halo rows each side, element conductivities and contributions and

@@ -54,8 +54,8 @@ struct LevelDev {
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
   int64_t team_bytes;
   // LDS tiles of grid-0 stencil passes: node rows (y) and planes (z) per
-  // tile, for 8-byte (index 0) and 4-byte (index 1) staged fields
-  int tile_y8, tile_z8, tile_y4, tile_z4;
+  // tile, [8-byte (0) or 4-byte (1) fields][2, 3 or 4 staged nodal fields]
+  int tile_y[2][3], tile_z[2][3];
   // node rows per tile of the fused two-sweep smoother pass (2D), for 8-byte
   // and 4-byte inner vectors
   int tile_p8, tile_p4;
