@@ -15,6 +15,8 @@ from the level's KL modes with standard normal coefficients drawn from their
 own seed, not from the workload's samples.
 
     python -m paper_1911_06066_amd.autotune --workload mlmc3_2d --out tuning.json
+
+With --refine the choice is then checked on the whole MLMC estimate (refine).
 """
 
 import argparse
@@ -118,6 +120,64 @@ def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, lo
     return rec
 
 
+def refine(wl, rec, modes, xi, steps=2, warmup=2, deltas=(-2, 2), log=print):
+    """Check the per-level sweep counts on the whole MLMC estimate.
+
+    Per-level times measured in isolation do not always carry over to the
+    fused launch: samples of all levels share the chip, and the iteration
+    counts can be sharply non-monotone in the sweep count.  Each level's count
+    is moved by each of `deltas` in turn, finest level first, and a move is kept
+    when the estimate's wall time per step falls by more than 1%.  modes[l],
+    xi[l]: device inputs of the estimate, as in the benchmark.
+    """
+    import time
+
+    import torch
+
+    from . import Context
+
+    N = list(wl["samples"])
+
+    def measure(tun):
+        ctx = Context(wl, precision=rec["precision"], level_tuning=tun)
+        for _ in range(warmup):
+            ctx.mlmc_estimate(N, modes, xi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.mlmc_estimate(N, modes, xi)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        ctx.close()
+        return ms
+
+    cur = [(e["smooth_sweeps"], e["cheb_ratio"], e["team_seconds"]) for e in rec["levels"]]
+    best = measure(cur)
+    trials = [{"sweeps": [c[0] for c in cur], "ms_per_step": best}]
+    log("refine: %s %.1f ms per step" % ([c[0] for c in cur], best))
+    for l in reversed(range(len(cur))):
+        base = cur
+        for d in deltas:
+            k = base[l][0] + d
+            if k < 1 or k > 32:
+                continue
+            cand = list(base)
+            cand[l] = (k,) + tuple(base[l][1:])
+            try:
+                ms = measure(cand)
+            except Exception as e:
+                log("refine: %s failed: %s" % ([c[0] for c in cand], e))
+                continue
+            trials.append({"sweeps": [c[0] for c in cand], "ms_per_step": ms})
+            log("refine: %s %.1f ms per step" % ([c[0] for c in cand], ms))
+            if ms < 0.99 * best:
+                best, cur = ms, cand
+    for e, c in zip(rec["levels"], cur):
+        e["smooth_sweeps"] = c[0]
+    rec["refine"] = {"steps": steps, "warmup": warmup, "trials": trials, "ms_per_step": best}
+    return rec
+
+
 def level_tuning(wl, precision=None, path=None):
     """(sweeps, ratio, team_seconds) per level from a tuning file, or None
     when there is no file or it was measured for other grids."""
@@ -148,9 +208,20 @@ def main():
     ap.add_argument("--samples", type=int, default=32)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--refine", action="store_true",
+                    help="then check each level's sweep count (+-2) on the whole MLMC estimate")
     a = ap.parse_args()
     wl = stinputs.workload(a.workload)
     rec = tune(wl, a.precision, a.samples, block=a.block, log=lambda s: print(s, flush=True))
+    if a.refine and wl.get("samples"):
+        import torch
+
+        from . import klmodes
+        dev = torch.device("cuda:0")
+        w = dict(wl, precision=rec["precision"])
+        modes = [torch.from_numpy(m).to(dev) for m in klmodes.workload_modes(w)]
+        xi = [torch.from_numpy(stinputs.xi(w["name"], l, n, w["n_modes"])).to(dev) for l, n in enumerate(w["samples"])]
+        refine(w, rec, modes, xi, log=lambda s: print(s, flush=True))
     out = a.out or tuning_path(wl["name"], rec["precision"])
     os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
     with open(out, "w") as f:
