@@ -173,6 +173,56 @@ def _brute_force(g, D):
     return M, K
 
 
+# ---------------------------------------------------------------------------
+# Fibre laws.  For linear fields u = x_p, v = x_q the Q1 stiffness gives
+# v^T K u = sum_e |e| (D_e)_qp exactly (their gradients are constant), and
+# D_xx, D_yy, D_xy are (s + t)/2 +- (s - t)/2 cos 2 theta and (s - t)/2 sin 2 theta.
+# With theta linear in one coordinate, the sum over element layers of
+# h cos(a + b z_c) at the layer midpoints z_c equals the exact integral of
+# cos(a + b z) divided by sinc(b h / 2) (the midpoint rule on a sinusoid),
+# which fixes the law, the axis it varies along and the evaluation point
+# (centroids, not nodes) in closed form.
+# ---------------------------------------------------------------------------
+def _layer_sums(a, b, length, h):
+    """(sum h cos(a + b z_c), sum h sin(a + b z_c)) over the layers of [0, length]."""
+    sinc = np.sin(b * h / 2) / (b * h / 2)
+    c = (np.sin(a + b * length) - np.sin(a)) / b / sinc
+    s = (np.cos(a) - np.cos(a + b * length)) / b / sinc
+    return c, s
+
+
+@pytest.mark.parametrize("law", ["diag2d", "rot3d", "x", "diag"])
+def test_fiber_laws_pinned_by_linear_field_energies(law):
+    dim = 2 if law == "diag2d" else 3
+    if dim == 2:
+        g = Grid((7, 5), (1.0, 0.8))
+    else:
+        g = Grid((5, 4, 7), (1.0, 0.9, 0.25))
+    sigma, tau = 1.7, 0.3
+    D = fem.diffusion_tensors(np.full(g.n_el, sigma), fem.fiber_angles(g, law), tau, dim)
+    K = fem.assemble_stiffness(g, D)
+    x = g.nodes()
+    E = np.array([[x[:, q] @ (K @ x[:, p]) for p in range(dim)] for q in range(dim)])
+    vol = float(np.prod(g.lengths))
+    if law == "diag2d":  # 2 theta = pi/2 + y
+        c, s = _layer_sums(np.pi / 2, 1.0, g.lengths[1], g.h[1])
+        c, s = g.lengths[0] * c, g.lengths[0] * s
+    elif law == "rot3d":  # 2 theta = -2 pi/3 + (4 pi/3) z / l_z
+        c, s = _layer_sums(-2 * np.pi / 3, 4 * np.pi / (3 * g.lengths[2]), g.lengths[2], g.h[2])
+        c, s = g.lengths[0] * g.lengths[1] * c, g.lengths[0] * g.lengths[1] * s
+    elif law == "x":
+        c, s = vol, 0.0
+    else:  # theta = pi/4: cos 2 theta = 0, sin 2 theta = 1
+        c, s = 0.0, vol
+    want = np.zeros((dim, dim))
+    want[0, 0] = 0.5 * (sigma + tau) * vol + 0.5 * (sigma - tau) * c
+    want[1, 1] = 0.5 * (sigma + tau) * vol - 0.5 * (sigma - tau) * c
+    want[0, 1] = want[1, 0] = 0.5 * (sigma - tau) * s
+    if dim == 3:
+        want[2, 2] = tau * vol
+    np.testing.assert_allclose(E, want, rtol=0, atol=1e-12 * sigma * vol)
+
+
 @pytest.mark.parametrize("shape", [(3, 3), (4, 3), (3, 3, 3)])
 def test_assembly_matches_brute_force(shape):
     g = Grid(shape, (1.0, 0.7, 0.5)[: len(shape)])
