@@ -90,7 +90,7 @@ typedef struct {
   int m;
   int smooth_sweeps;          /* Jacobi sweeps on the level's coarsest V-cycle grid, 0 .. 32 */
   double cheb_ratio;          /* Chebyshev interval ratio, 0 or > 1 */
-  double team_seconds[16];    /* measured device seconds per sample with a team of g+1 workgroups
+  double team_seconds[32];    /* measured device seconds per sample with a team of g+1 workgroups
                                  (0 = unknown); the MLMC scheduler's starting cost model, refined by
                                  the measurements of every launch */
 } stm_level;
@@ -128,9 +128,14 @@ typedef struct {
   double gmres_rtol;          /* relative Krylov residual: 1e-10 (fp64), 1e-5 (mixed) */
   int gmres_restart;          /* Krylov dimension of one linear solve: 16, at most 30; an unfinished
                                  solve is continued by the next Newton step */
-  int mg_levels;              /* multigrid grids of the V-cycle: 1 (smoothing on the level's grid only).
-                                 Other values (-1: as deep as the grid allows) are rejected with
-                                 STM_E_UNSUPPORTED: the multi-grid kernel variant is disabled */
+  int mg_levels;              /* grids of the geometric-multigrid V-cycle that preconditions each slab's
+                                 GMRES: 1 (default; Chebyshev-weighted sweeps on the level's grid only),
+                                 2 .. 8, or -1 (as deep as the grid allows).  Coarsening halves every axis
+                                 while all stay odd with >= 5 nodes in x, y (>= 3 in z).  Coarse operators
+                                 are rediscretised: element conductivity the mean of its children, the
+                                 coarse grid's own fibre angles, reaction weights injected from the level's
+                                 grid.  Restriction is full weighting (the transpose of Q1 interpolation).
+                                 A level with coarse grids is solved by one-workgroup teams */
   int smooth_steps;           /* weighted-Jacobi sweeps before and after the coarse correction: 2 */
   double smooth_omega;        /* fixed Jacobi weight (smoother 0): 0.7 */
   int coarse_sweeps;          /* weighted-Jacobi sweeps on the coarsest grid (the only grid when
@@ -154,6 +159,9 @@ typedef struct {
   int tau_relative;           /* 0: tau_e = transverse_ratio sigma_f0; 1: tau_e = transverse_ratio sigma_e */
   int ic_kind;                /* stm_ic_kind: 0 ball */
   int qoi;                    /* stm_qoi of stm_mlmc_estimate: 0 activation map */
+  int newton_damping;         /* 0 (default) or 1: a slab's Newton step is halved (down to 1/64 of it)
+                                 while the FP64 residual 2-norm it leads to exceeds the last accepted
+                                 one; -1: full Newton steps */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */
@@ -169,6 +177,14 @@ typedef struct {
   double phase_seconds[8];    /* per-phase device time (residual, smoothing, Arnoldi stencil, dots,
                                  orthogonalisation, update, -, -) in libraries built with phase
                                  timers; zero otherwise */
+  double model_bytes;         /* bytes of the solve by per-node word counts of the method's steps,
+                                 n nodes: 4 float64 words per Newton residual; per Krylov iteration j
+                                 (0-based within its linear solve) 4 words for the Jacobian product,
+                                 5 per smoother sweep (on every V-cycle grid, weighted by its nodes)
+                                 and 2j + 3 for the Arnoldi step, in the inner precision.  Passes the
+                                 kernel fuses are counted as the separate steps they replace */
+  int64_t damped_steps;       /* Newton steps halved because the residual 2-norm grew (each halving
+                                 costs one residual evaluation, counted in newton_iters) */
 } stm_solve_stats;
 
 /* Device time of the last call's phases, measured with HIP events on the context stream. */
@@ -181,6 +197,7 @@ typedef struct {
   int solve_teams;            /* teams (samples in flight) of the last solver launch */
   int solve_blocks;           /* workgroups of the last solver launch */
   int solve_block;            /* threads per workgroup of the last solver launch */
+  double solve_bytes_model;   /* bytes of the solver launches by the per-step word model (model_bytes) */
 } stm_timings;
 
 /* Output of stm_mlmc_estimate. Device arrays are caller-owned, n_L = nodes of the finest level. */
@@ -205,6 +222,7 @@ typedef struct {
   int worst_status;
   double algorithmic_bytes;   /* over all solves, as in stm_solve_stats */
   int64_t dof_steps;          /* sum over solves of nodes x time steps (both pair members) */
+  double model_bytes;         /* over all solves, by the per-step word model of stm_solve_stats */
 } stm_mlmc_result;
 
 typedef struct stm_ctx stm_ctx;

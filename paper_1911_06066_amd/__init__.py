@@ -14,6 +14,7 @@ loudly when it has not been built.
 """
 
 import ctypes
+import sys
 
 from . import _lib
 
@@ -62,7 +63,7 @@ def problem_from_workload(wl, **overrides):
             p.levels[i].smooth_sweeps = int(t[0])
             p.levels[i].cheb_ratio = float(t[1])
             for g, sec in enumerate((t[2] if len(t) > 2 else None) or []):
-                if g < 16:
+                if g < 32:
                     p.levels[i].team_seconds[g] = float(sec)
     p.n_modes = wl["n_modes"]
     p.theta = wl.get("theta", 1.0)
@@ -111,11 +112,27 @@ class Context:
         self.sizes = [self.level_size(l) for l in range(self.problem.n_levels)]
 
     def close(self):
+        """Release the library context (synchronises its stream).  Call it, or use
+        the context as a `with` block, before the process exits: the library's
+        HIP calls must not run while the interpreter and the HIP runtime shut
+        down."""
         if getattr(self, "h", None):
             self.lib.stm_destroy(self.h)
             self.h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
+        # During interpreter shutdown the HIP runtime may already be tearing
+        # down (or a profiler's tool library finalising); an unclosed context
+        # is then left to the process exit instead of calling into HIP.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -169,7 +186,9 @@ class Context:
         return out, [dict(status=s.status, newton_max_per_slab=s.newton_max_per_slab,
                           newton_iters=s.newton_iters, krylov_iters=s.krylov_iters,
                           final_step=s.final_step, device_seconds=s.device_seconds,
-                          algorithmic_bytes=s.algorithmic_bytes, phase_seconds=list(s.phase_seconds))
+                          algorithmic_bytes=s.algorithmic_bytes, model_bytes=s.model_bytes,
+                          damped_steps=s.damped_steps,
+                          phase_seconds=list(s.phase_seconds))
                      for s in st_arr[:S]]
 
     def activation_map(self, level, u, out=None):
@@ -227,4 +246,4 @@ class Context:
                     bias_estimate=res.bias_estimate, newton_iters=res.newton_iters,
                     krylov_iters=res.krylov_iters, censored=res.censored, rounds=res.rounds,
                     worst_status=res.worst_status, algorithmic_bytes=res.algorithmic_bytes,
-                    dof_steps=res.dof_steps)
+                    model_bytes=res.model_bytes, dof_steps=res.dof_steps)

@@ -25,7 +25,7 @@ QOIS = {"activation": 0, "spacetime": 1}
 class StmLevel(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("m", ctypes.c_int),
                 ("smooth_sweeps", ctypes.c_int), ("cheb_ratio", ctypes.c_double),
-                ("team_seconds", ctypes.c_double * 16)]
+                ("team_seconds", ctypes.c_double * 32)]
 
 
 class StmProblem(ctypes.Structure):
@@ -61,6 +61,7 @@ class StmProblem(ctypes.Structure):
         ("tau_relative", ctypes.c_int),
         ("ic_kind", ctypes.c_int),
         ("qoi", ctypes.c_int),
+        ("newton_damping", ctypes.c_int),
     ]
 
 
@@ -71,6 +72,8 @@ class StmSolveStats(ctypes.Structure):
         ("final_step", ctypes.c_double), ("device_seconds", ctypes.c_double),
         ("algorithmic_bytes", ctypes.c_double),
         ("phase_seconds", ctypes.c_double * 8),
+        ("model_bytes", ctypes.c_double),
+        ("damped_steps", ctypes.c_int64),
     ]
 
 
@@ -79,6 +82,7 @@ class StmTimings(ctypes.Structure):
         ("kl_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("stats_ms", ctypes.c_double),
         ("solve_bytes", ctypes.c_double), ("solve_launches", ctypes.c_int),
         ("solve_teams", ctypes.c_int), ("solve_blocks", ctypes.c_int), ("solve_block", ctypes.c_int),
+        ("solve_bytes_model", ctypes.c_double),
     ]
 
 
@@ -94,6 +98,7 @@ class StmMlmcResult(ctypes.Structure):
         ("censored", ctypes.c_int64),
         ("rounds", ctypes.c_int), ("worst_status", ctypes.c_int),
         ("algorithmic_bytes", ctypes.c_double), ("dof_steps", ctypes.c_int64),
+        ("model_bytes", ctypes.c_double),
     ]
 
 

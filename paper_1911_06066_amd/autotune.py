@@ -24,6 +24,8 @@ import json
 import os
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(HERE, "tuning")
 
@@ -32,8 +34,17 @@ CANDIDATES = [(8, 10.0), (10, 10.0), (12, 10.0), (14, 10.0), (16, 10.0), (16, 20
 # 10 on the 65x65x17 slab), so their list spans ratios 10 to 30.
 CANDIDATES_3D = [(8, 10.0), (12, 10.0), (8, 20.0), (12, 20.0), (16, 20.0), (24, 20.0), (12, 30.0), (16, 30.0),
                  (24, 30.0)]
-TEAM_SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16)
-MAX_TEAM = 16
+TEAM_SIZES = (1, 2, 3, 4, 6, 8, 10, 12, 16, 24, 32)
+MAX_TEAM = 32
+LARGE_TEAM_SIZES = (8, 16, 24, 32)
+# Levels of more than LARGE nodes x steps per sample (the finest 3D grids,
+# about 90 workgroup-seconds per sample on one workgroup) are tuned on
+# LARGE_SAMPLES samples solved by teams of the largest size, over a causal
+# prefix of LARGE_PREFIX steps with the level's dt (the smoother's effect per
+# slab does not depend on the horizon); their team table holds LARGE_TEAM_SIZES.
+LARGE = 1e8
+LARGE_SAMPLES = 4
+LARGE_PREFIX = 128
 
 
 def tuning_path(workload, precision):
@@ -60,17 +71,28 @@ def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, lo
     M = wl["n_modes"]
     rec = {"workload": wl["name"], "precision": precision, "device": torch.cuda.get_device_name(0),
            "samples": samples, "seed": seed, "levels": []}
+    counts = wl.get("samples")
     for l in range(len(wl["levels"])):
-        S = max(2, min(samples, int(wl["samples"][l]) if "samples" in wl else samples))
+        S = max(2, min(samples, int(counts[l]) if counts else samples))
+        m = int(wl["steps"][l])
+        gmax = max(1, min(MAX_TEAM, int(wl["levels"][l][1]) // 3))
+        large = float(np.prod(wl["levels"][l])) * m > LARGE
+        wl_t, G_t, scale = wl, 1, 1.0
+        if large:
+            S, G_t = min(S, LARGE_SAMPLES), gmax
+            k = min(m, LARGE_PREFIX)
+            wl_t = dict(wl, steps=list(wl["steps"]), T=wl["T"] * k / m)
+            wl_t["steps"][l] = k
+            scale = m / k
         xi = torch.randn(S, M, generator=gen, dtype=torch.float64).to(dev)
         results = []
         for sweeps, ratio in candidates:
             tune_l = [None] * len(wl["levels"])
             tune_l[l] = (sweeps, ratio)
-            over = dict(precision=precision, level_tuning=tune_l, team_size=1, max_lanes=S)
+            over = dict(precision=precision, level_tuning=tune_l, team_size=G_t, max_lanes=S * G_t)
             if block:
                 over["block_threads"] = block
-            ctx = Context(wl, **over)
+            ctx = Context(wl_t, **over)
             sig = ctx.kl_synthesize(l, modes[l], xi)
             t0 = time.perf_counter()
             try:
@@ -81,8 +103,11 @@ def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, lo
                 st, ok = [], False
             wall = time.perf_counter() - t0
             r = {"smooth_sweeps": sweeps, "cheb_ratio": ratio, "ok": ok, "wall_s": wall}
+            if large:
+                r["team"] = G_t
+                r["prefix_steps"] = wl_t["steps"][l]
             if st:
-                r["seconds_per_sample"] = sum(s["device_seconds"] for s in st) / len(st)
+                r["seconds_per_sample"] = scale * sum(s["device_seconds"] for s in st) / len(st)
                 r["newton_per_sample"] = sum(s["newton_iters"] for s in st) / len(st)
                 r["krylov_per_sample"] = sum(s["krylov_iters"] for s in st) / len(st)
             results.append(r)
@@ -94,13 +119,13 @@ def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, lo
         entry["smooth_sweeps"] = best["smooth_sweeps"] if best else 0
         entry["cheb_ratio"] = best["cheb_ratio"] if best else 0.0
         entry["results"] = results
-        # seconds per sample against team size, with the chosen smoother
+        # seconds per sample against team size, with the chosen smoother (a
+        # large level: the full horizon at the large team sizes only)
         team = [0.0] * MAX_TEAM
         if best:
-            gmax = max(1, min(MAX_TEAM, int(wl["levels"][l][1]) // 3))
             tune_l = [None] * len(wl["levels"])
             tune_l[l] = (best["smooth_sweeps"], best["cheb_ratio"])
-            for G in TEAM_SIZES:
+            for G in (LARGE_TEAM_SIZES if large else TEAM_SIZES):
                 if G > gmax:
                     break
                 over = dict(precision=precision, level_tuning=tune_l, team_size=G, max_lanes=S * G)
@@ -117,6 +142,39 @@ def tune(wl, precision=None, samples=32, candidates=None, seed=4242, block=0, lo
                 log("level %d team %d: %.4f s per sample" % (l, G, team[G - 1]))
         entry["team_seconds"] = team
         rec["levels"].append(entry)
+    return rec
+
+
+def measure_teams(wl, rec, level, samples=None, seed=4343, log=print):
+    """Re-measure one level's team table (seconds per sample against team
+    size, full horizon) with the smoother the record holds for it."""
+    import torch
+
+    from . import Context, klmodes
+
+    dev = torch.device("cuda:0")
+    precision = rec["precision"]
+    modes = torch.from_numpy(klmodes.workload_modes(wl)[level]).to(dev)
+    M = wl["n_modes"]
+    e = rec["levels"][level]
+    m = int(wl["steps"][level])
+    gmax = max(1, min(MAX_TEAM, int(wl["levels"][level][1]) // 3))
+    large = float(np.prod(wl["levels"][level])) * m > LARGE
+    S = samples or (LARGE_SAMPLES if large else 32)
+    xi = torch.randn(S, M, generator=torch.Generator().manual_seed(seed), dtype=torch.float64).to(dev)
+    tune_l = [None] * len(wl["levels"])
+    tune_l[level] = (e["smooth_sweeps"], e["cheb_ratio"])
+    team = list(e.get("team_seconds", [])) + [0.0] * MAX_TEAM
+    team = team[:MAX_TEAM]
+    for G in (LARGE_TEAM_SIZES if large else TEAM_SIZES):
+        if G > gmax:
+            break
+        with Context(wl, precision=precision, level_tuning=tune_l, team_size=G, max_lanes=S * G) as ctx:
+            sig = ctx.kl_synthesize(level, modes, xi)
+            _, st = ctx.st_solve(level, sig)
+        team[G - 1] = sum(s["device_seconds"] for s in st) / len(st)
+        log("level %d team %d: %.4f s per sample" % (level, G, team[G - 1]))
+    e["team_seconds"] = team
     return rec
 
 
@@ -162,7 +220,7 @@ def refine(wl, rec, modes, xi, steps=2, warmup=2, deltas=(-2, 2), log=print):
             if k < 1 or k > 32:
                 continue
             cand = list(base)
-            cand[l] = (k,) + tuple(base[l][1:])
+            cand[l] = (k, base[l][1], None)  # team times of another sweep count do not apply
             try:
                 ms = measure(cand)
             except Exception as e:
@@ -173,7 +231,12 @@ def refine(wl, rec, modes, xi, steps=2, warmup=2, deltas=(-2, 2), log=print):
             if ms < 0.99 * best:
                 best, cur = ms, cand
     for e, c in zip(rec["levels"], cur):
-        e["smooth_sweeps"] = c[0]
+        if e["smooth_sweeps"] != c[0]:
+            # its team table was measured at the old sweep count: cleared, so
+            # that the scheduler starts from its model and learns the times
+            e["smooth_sweeps"] = c[0]
+            e["team_seconds"] = [0.0] * MAX_TEAM
+            e["team_seconds_note"] = "cleared: the refinement changed the sweep count"
     rec["refine"] = {"steps": steps, "warmup": warmup, "trials": trials, "ms_per_step": best}
     return rec
 
@@ -210,8 +273,21 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--refine", action="store_true",
                     help="then check each level's sweep count (+-2) on the whole MLMC estimate")
+    ap.add_argument("--teams-only", type=int, default=-1, metavar="LEVEL",
+                    help="only re-measure this level's team table in the existing tuning file")
     a = ap.parse_args()
     wl = stinputs.workload(a.workload)
+    if a.teams_only >= 0:
+        precision = a.precision or wl.get("precision", "fp64")
+        path = tuning_path(wl["name"], precision)
+        with open(path) as f:
+            rec = json.load(f)
+        measure_teams(wl, rec, a.teams_only, log=lambda s: print(s, flush=True))
+        out = a.out or path
+        with open(out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print("wrote", out, flush=True)
+        return
     rec = tune(wl, a.precision, a.samples, block=a.block, log=lambda s: print(s, flush=True))
     if a.refine and wl.get("samples"):
         import torch

@@ -9,6 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstmlmc.so")
+CAL_LIB = os.path.join(HERE, "libstmcal.so")  # copy kernels for counter calibration (not the solver interface)
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["st_solver.hip", "kl_gemm.hip", "qoi_mlmc.hip", "stm_api.hip"]
@@ -55,6 +56,17 @@ def build(verbose=False, lib=LIB, defines=(), build_dir=BUILD_DIR):
     os.replace(tmp, lib)
     if verbose:
         print("built", lib)
+    if lib != LIB:
+        return lib
+    cal_obj = _compile("copycal.hip", extra, build_dir)
+    tmp = CAL_LIB + ".tmp"
+    r = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, cal_obj],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stderr)
+    os.replace(tmp, CAL_LIB)
+    if verbose:
+        print("built", CAL_LIB)
     return lib
 
 

@@ -16,17 +16,18 @@
 // from already computed samples) or, without one, u_{k-1}.  The activation
 // map is updated as each slab is accepted.
 //
-// Teams: with G = 1 a workgroup owns the sample.  With G > 1 (single-grid
-// V-cycle only) member r owns node rows [r ny / G, (r+1) ny / G) of the grid;
+// Teams: with G = 1 a workgroup owns the sample.  With G > 1 (levels without
+// coarse V-cycle grids) member r owns node rows [r ny / G, (r+1) ny / G) of the grid;
 // passes end with a team barrier (agent-scope release/acquire around an
 // atomic counter, bounded wait) and reductions sum the members' partials in
 // rank order, so every member takes identical control-flow decisions.  Such
 // launches are cooperative: co-residency is guaranteed or the launch fails.
 //
-// Memory: stencil passes on the level's grid stage tiles of their nodal
-// fields and element conductivities into LDS with batched loads, compute each
-// element's vertex contributions once (sum factorisation) and gather them per
-// node; coarse multigrid grids are read from global memory.
+// Memory: stencil passes stage tiles of their nodal fields and element
+// conductivities into LDS with batched loads, compute each element's vertex
+// contributions once (sum factorisation) and gather them per node, on the
+// level's grid and on every coarse V-cycle grid alike; restriction and
+// prolongation between grids are plain loops over global memory.
 //
 // Precision: the residual R_k, the update u += delta, the activation
 // interpolation and every stored solution are float64.  The Krylov and
@@ -62,6 +63,7 @@ __device__ __forceinline__ double uni(double v) {
 }
 
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
+constexpr double kMinStep = 1.0 / 64;  // smallest damped fraction of a Newton step
 constexpr unsigned kSpinLimit = 1u << 25;
 
 template <int DIM>
@@ -160,14 +162,23 @@ struct Team {
   long long* ph;         // shared per-phase tick accumulators
 #endif
 
-  __device__ __forceinline__ double dbytes(int l) const {
-    return l == 0 ? 8.0 * L->g[0].ne : 4.0 * sizeof(TI) * L->g[l].ne;
+  __device__ __forceinline__ double dbytes(int l) const { return 8.0 * L->g[l].ne; }
+  __device__ __forceinline__ TI* mgX(int l) const {
+    return l == 0 ? nullptr : reinterpret_cast<TI*>(work + L->off_mgX[l]);
   }
-  __device__ TI* mgX(int l) const { return l == 0 ? nullptr : reinterpret_cast<TI*>(work + L->off_mgX[l]); }
-  __device__ TI* mgT(int l) const { return reinterpret_cast<TI*>(work + L->off_mgT[l]); }
-  __device__ TI* mgB(int l) const { return reinterpret_cast<TI*>(work + L->off_mgB[l]); }
-  __device__ TI* mgW(int l) const { return reinterpret_cast<TI*>(work + L->off_mgW[l]); }
-  __device__ TI* mgD(int l) const { return reinterpret_cast<TI*>(work + L->off_mgD[l]); }
+  __device__ __forceinline__ TI* mgT(int l) const { return reinterpret_cast<TI*>(work + L->off_mgT[l]); }
+  __device__ __forceinline__ TI* mgB(int l) const { return reinterpret_cast<TI*>(work + L->off_mgB[l]); }
+  __device__ __forceinline__ TI* mgW(int l) const { return reinterpret_cast<TI*>(work + L->off_mgW[l]); }
+  // inverse slab diagonal, conductivities and stiffness diagonal of grid l
+  __device__ __forceinline__ TI* mgI(int l) const {
+    return l == 0 ? dinv : reinterpret_cast<TI*>(work + L->off_mgI[l]);
+  }
+  __device__ __forceinline__ const double* mgS(int l) const {
+    return l == 0 ? sigma : reinterpret_cast<const double*>(work + L->off_mgS[l]);
+  }
+  __device__ __forceinline__ double* mgK(int l) const {
+    return l == 0 ? kdiag0 : reinterpret_cast<double*>(work + L->off_mgK[l]);
+  }
 
   // ---- team synchronisation and reductions --------------------------------
   // Every wave first waits until its own global stores have completed (a
@@ -175,7 +186,7 @@ struct Team {
   // the block's writes at agent scope (write-back of the L2), arrives, waits
   // for the other members and acquires, which invalidates the CU's caches for
   // every wave of the block.
-  __device__ void team_barrier() const {
+  __device__ __forceinline__ void team_barrier() const {
     if (G > 1) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (G > 1) {
@@ -204,7 +215,7 @@ struct Team {
   __device__ __forceinline__ void sync() const { team_barrier(); }
 
   template <int NV>
-  __device__ void tsum(double (&v)[NV]) const {
+  __device__ __forceinline__ void tsum(double (&v)[NV]) const {
     block_sum<BLOCK, NV>(v, red);
     if (G == 1) return;
     double* slot = part + (size_t)(rslot & 1) * G * kPartStride;
@@ -221,7 +232,7 @@ struct Team {
       v[i] = s;
     }
   }
-  __device__ double tmax(double v) const {
+  __device__ __forceinline__ double tmax(double v) const {
     v = block_max<BLOCK>(v, red);
     if (G == 1) return v;
     double* slot = part + (size_t)(rslot & 1) * G * kPartStride;
@@ -263,21 +274,25 @@ struct Team {
   // node.  Phases A and B read LDS only; every LDS array is laid out so that
   // consecutive lanes touch consecutive words.  Index decoding uses exact
   // multiply-high division.  Ends with a team barrier.
+  // Grid l >= 1 (a coarse V-cycle grid, one-workgroup teams) is staged the
+  // same way, with its own conductivities, fibre rows and tiles, every row
+  // owned.
   template <typename T, typename KV, typename MV, typename Body>
-  __device__ void staged(const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
+  __device__ __forceinline__ void staged(int l, const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
                          const T* __restrict__ f3, KV kval, MV mval, Body body) const {
     constexpr int NV = (DIM == 3) ? 8 : 4;
     constexpr int U = 4;                      // batched loads per thread in the staging loop
     constexpr int UA = (DIM == 3) ? 1 : 2;    // independent elements per thread in phase A
-    const GridDev& g = L->g[0];
+    const GridDev& g = L->g[l];
     const int nx = g.nx, EX = g.ex;
     const unsigned mnx = g.mnx, mex = g.mex;
     const int nf = 2 + (f2 ? 1 : 0) + (f3 ? 1 : 0);
-    const int Ry = L->tile_y[sizeof(T) == 8 ? 0 : 1][nf - 2];
-    const int Rz = (DIM == 3) ? L->tile_z[sizeof(T) == 8 ? 0 : 1][nf - 2] : 1;
+    const int Ry = L->tile_y[l][sizeof(T) == 8 ? 0 : 1][nf - 2];
+    const int Rz = (DIM == 3) ? L->tile_z[l][sizeof(T) == 8 ? 0 : 1][nf - 2] : 1;
     const int nzz = (DIM == 3) ? g.nz : 1;
-    const double* __restrict__ sg = sigma;
-    const double* __restrict__ fib = L->fib;
+    const int jb0 = l == 0 ? this->jb0 : 0, jb1 = l == 0 ? this->jb1 : g.ny;
+    const double* __restrict__ sg = mgS(l);
+    const double* __restrict__ fib = L->fib[l];
     const double tau = prm.tau, zr = prm.zr;
     const T hx = T(g.hx), hy = T(g.hy), hz = T(g.hz);
     const T cxx = (DIM == 3) ? hy * hz / (T(36) * hx) : hy / (T(6) * hx);
@@ -460,9 +475,9 @@ struct Team {
     if (G > 1) team_barrier();
   }
 
-  // number of elements adjacent to node (i, j, k) of grid 0
-  __device__ __forceinline__ int nel0(int i, int j, int k) const {
-    const GridDev& g = L->g[0];
+  // number of elements adjacent to node (i, j, k) of grid l
+  __device__ __forceinline__ int nel(int l, int i, int j, int k) const {
+    const GridDev& g = L->g[l];
     int c = ((i > 0) + (i < g.nx - 1)) * ((j > 0) + (j < g.ny - 1));
     if constexpr (DIM == 3) c *= (k > 0) + (k < g.nz - 1);
     return c;
@@ -473,81 +488,39 @@ struct Team {
     return (DIM == 3) ? TI(8.0 * g.hx * g.hy * g.hz / 216.0) : TI(4.0 * g.hx * g.hy / 36.0);
   }
 
-  // y = A_l x at node idx of a coarse grid l >= 1 (global memory)
-  __device__ __forceinline__ TI apply_coarse(int l, const TI* __restrict__ x, int idx, TI* diag) const {
-    const GridDev& g = L->g[l];
-    const TI* __restrict__ w = mgW(l);
-    const TI* __restrict__ D = mgD(l);
-    int i, j, k;
-    decode<DIM>(g, idx, i, j, k);
-    auto flat = [&](int a, int b, int c) { return (DIM == 3) ? ((c * g.ny + b) * g.nx + a) : (b * g.nx + a); };
-    return apply_at<TI, DIM>(g, i, j, k, [&](int a, int b, int c) { const int q = flat(a, b, c); return w[q] * x[q]; },
-                             [&](int a, int b, int c) { return x[flat(a, b, c)]; },
-                             [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); }, w[idx],
-                             diag);
-  }
-
-  // diagonal of A_l at node idx of a coarse grid (global memory)
-  __device__ __forceinline__ TI diag_coarse(int l, int idx) const {
-    const GridDev& g = L->g[l];
-    const TI* __restrict__ w = mgW(l);
-    const TI* __restrict__ D = mgD(l);
-    int i, j, k;
-    decode<DIM>(g, idx, i, j, k);
-    TI d;
-    auto z = [&](int, int, int) { return TI(0); };
-    apply_at<TI, DIM>(g, i, j, k, z, z, [&](int ex, int ey, int ez) { return tensor_stored<TI, DIM>(D, g, ex, ey, ez); },
-                      w[idx], &d);
-    return d;
-  }
-
   // ---- smoothing -----------------------------------------------------------
-  // out = x + om (b - A x) / diag ;  x == null means x = 0 (out = om b / diag)
-  __device__ void jacobi(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out,
+  // out = x + om (b - A x) / diag on grid l;  x == null means x = 0 (out = om b / diag)
+  __device__ __forceinline__ void jacobi(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out,
                          TI om) const {
     const int n = L->g[l].n;
     bytes = uni(bytes + ((x ? 5.0 : 4.0) * sizeof(TI) * n + (x ? dbytes(l) : 0.0)));
-    if (l == 0) {
-      const TI* __restrict__ w = mgW(0);
-      if (!x) {
-        const int nb = nband();
-        const TI* __restrict__ di = dinv;
-        for (int qb = threadIdx.x; qb < nb; qb += BLOCK * 4) {
-          TI rb[4], rd[4];
+    const TI* __restrict__ w = mgW(l);
+    const TI* __restrict__ di = mgI(l);
+    if (!x) {
+      const int nb = l == 0 ? nband() : n;
+      for (int qb = threadIdx.x; qb < nb; qb += BLOCK * 4) {
+        TI rb[4], rd[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int q = qb + v * BLOCK;
-            if (q < nb) {
-              const int idx = bidx(q);
-              rb[v] = b[idx];
-              rd[v] = di[idx];
-            }
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int q = qb + v * BLOCK;
-            if (q < nb) out[bidx(q)] = om * rb[v] * rd[v];
+        for (int v = 0; v < 4; ++v) {
+          const int q = qb + v * BLOCK;
+          if (q < nb) {
+            const int idx = l == 0 ? bidx(q) : q;
+            rb[v] = b[idx];
+            rd[v] = di[idx];
           }
         }
-        sync();
-        return;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = qb + v * BLOCK;
+          if (q < nb) out[l == 0 ? bidx(q) : q] = om * rb[v] * rd[v];
+        }
       }
-      staged<TI>(
-          x, w, b, dinv, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
-          [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
+      sync();
       return;
     }
-    if constexpr (!MG) return;
-    if (!x) {
-      for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = om * b[idx] / diag_coarse(l, idx);
-    } else {
-      for (int idx = threadIdx.x; idx < n; idx += BLOCK) {
-        TI d;
-        const TI ax = apply_coarse(l, x, idx, &d);
-        out[idx] = x[idx] + om * (b[idx] - ax) / d;
-      }
-    }
-    __syncthreads();
+    staged<TI>(
+        l, x, w, b, di, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
+        [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
   }
 
   // Two Jacobi sweeps on grid 0 in one pass over the tiles (2D):
@@ -559,7 +532,7 @@ struct Team {
   // result equals two single sweeps.  x == null stands for the sweep from zero,
   // x = om0 b dinv, formed while staging (three sweeps in the pass).  out must
   // not alias x.  Ends with a team barrier.
-  __device__ void jacobi_pair(const TI* __restrict__ x, const TI* __restrict__ b, TI* __restrict__ out, TI om0,
+  __device__ __forceinline__ void jacobi_pair(const TI* __restrict__ x, const TI* __restrict__ b, TI* __restrict__ out, TI om0,
                               TI om1, TI om2) const {
     static_assert(DIM == 2, "the fused sweep pair is 2D");
     using T = TI;
@@ -574,7 +547,7 @@ struct Team {
     const unsigned mnx = g.mnx, mex = g.mex;
     const int Ry = sizeof(T) == 8 ? L->tile_p8 : L->tile_p4;
     const double* __restrict__ sg = sigma;
-    const double* __restrict__ fib = L->fib;
+    const double* __restrict__ fib = L->fib[0];
     const double tau = prm.tau, zr = prm.zr;
     const T hx = T(g.hx), hy = T(g.hy);
     const T cxx = hy / (T(6) * hx), cyy = hx / (T(6) * hy), cm = hx * hy / T(36);
@@ -719,7 +692,7 @@ struct Team {
   // ones alternate between two LDS vectors, and the last is written to out.
   // Each sweep takes the operations of a single sweep in the same order.  Ends
   // with a workgroup barrier.
-  __device__ void jacobi_resident(const TI* __restrict__ b, TI* __restrict__ out, int nc) const {
+  __device__ __forceinline__ void jacobi_resident(const TI* __restrict__ b, TI* __restrict__ out, int nc) const {
     static_assert(DIM == 2, "the resident smoother is 2D");
     using T = TI;
     constexpr int NV = 4;
@@ -780,7 +753,7 @@ struct Team {
         if (q < nse) ls[q] = rs[u];
       }
     }
-    for (int q = threadIdx.x; q < kFibStride * g.ey; q += BLOCK) lf[q] = L->fib[q];
+    for (int q = threadIdx.x; q < kFibStride * g.ey; q += BLOCK) lf[q] = L->fib[0][q];
     __syncthreads();
     // ---- sweep 1 from x = 0 ----
     {
@@ -853,23 +826,17 @@ struct Team {
     }
   }
 
-  __device__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
+  __device__ __forceinline__ void residual_inner(int l, const TI* __restrict__ b, const TI* __restrict__ x, TI* __restrict__ out) const {
     const int n = L->g[l].n;
     bytes = uni(bytes + (4.0 * sizeof(TI) * n + dbytes(l)));
-    if (l == 0) {
-      const TI* __restrict__ w = mgW(0);
-      staged<TI>(
-          x, w, b, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
-          [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
-      return;
-    }
-    if constexpr (!MG) return;
-    for (int idx = threadIdx.x; idx < n; idx += BLOCK) out[idx] = b[idx] - apply_coarse(l, x, idx, nullptr);
-    __syncthreads();
+    const TI* __restrict__ w = mgW(l);
+    staged<TI>(
+        l, x, w, b, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+        [](TI a, TI ww) { return ww * a; }, [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
   }
 
   // coarse[l+1] = P^T fine[l]  (full weighting, transpose of Q1 interpolation); G == 1 only
-  __device__ void restrict_to(int l, const TI* __restrict__ rf, TI* __restrict__ bc) const {
+  __device__ __forceinline__ void restrict_to(int l, const TI* __restrict__ rf, TI* __restrict__ bc) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
     bytes = uni(bytes + (double(sizeof(TI)) * (gf.n + gc.n)));
@@ -902,7 +869,7 @@ struct Team {
   }
 
   // fine[l] += P coarse[l+1]  (Q1 interpolation of nested grids); G == 1 only
-  __device__ void prolong_add(int l, const TI* __restrict__ xc, TI* __restrict__ xf) const {
+  __device__ __forceinline__ void prolong_add(int l, const TI* __restrict__ xc, TI* __restrict__ xf) const {
     const GridDev& gf = L->g[l];
     const GridDev& gc = L->g[l + 1];
     bytes = uni(bytes + (double(sizeof(TI)) * (2.0 * gf.n + gc.n)));
@@ -934,7 +901,7 @@ struct Team {
   // between a level's two buffers so that buf[1] is the level's output for any
   // sweep count; the coarsest grid's sweeps start in the buffer that makes the
   // last one land in buf[1].
-  __device__ void vcycle(const TI* __restrict__ b0, TI* __restrict__ out0) const {
+  __device__ __forceinline__ void vcycle(const TI* __restrict__ b0, TI* __restrict__ out0) const {
     if constexpr (!MG) {
       // sweep s (1-based) of nc writes buf[(nc - s + 1) % 2]: the last one out0
       TI* buf[2] = {mgT(0), out0};
@@ -998,58 +965,46 @@ struct Team {
     }
   }
 
-  // lmax of D^-1 A_l by power iteration from a smooth + checkerboard start.
+  // lmax of D^-1 A_l by power iteration.
   // Uses buffers x0, x1 of grid l.  Returns the estimate (team-uniform).
-  __device__ double power_lmax(int l, TI* x0, TI* x1) const {
+  __device__ __forceinline__ double power_lmax(int l, TI* x0, TI* x1) const {
     const GridDev& g = L->g[l];
-    auto init = [&](int idx) {
-      int i, j, k;
-      decode<DIM>(g, idx, i, j, k);
-      x0[idx] = TI(1.0 + 0.5 * (((i + j + k) & 1) ? -1.0 : 1.0));
-    };
-    if (l == 0) {
-      for (int q = threadIdx.x; q < nband(); q += BLOCK) init(bidx(q));
-      sync();
-    } else {
-      for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) init(idx);
-      __syncthreads();
+    const int nb = l == 0 ? nband() : g.n;  // coarse grids: one-workgroup teams own every node
+    // Start: a constant plus per-node pseudo-random values in [-1/2, 1/2) (a
+    // multiplicative hash of the node index, the same on every member).  When
+    // the stiffness dominates A, the largest eigenvalues of D^-1 A belong to
+    // modes that alternate along one axis only (Q1 in 2D and 3D); a start
+    // without them, such as a checkerboard, underestimates lmax, and the
+    // Chebyshev sweeps then amplify those modes.  Pseudo-random values contain
+    // every mode.
+    for (int q = threadIdx.x; q < nb; q += BLOCK) {
+      const int idx = l == 0 ? bidx(q) : q;
+      const unsigned hsh = (unsigned)idx * 2654435761u;
+      x0[idx] = TI(1.0 + double(hsh >> 8) * (1.0 / 16777216.0) - 0.5);
     }
+    sync();
     double lam = 0.0;
+    const TI* __restrict__ w = mgW(l);
+    const TI* __restrict__ di = mgI(l);
     for (int it = 0; it < prm.power_iters; ++it) {
       double nn[2] = {0.0, 0.0};
-      if (l == 0) {
-        const TI* __restrict__ w = mgW(0);
-        staged<TI>(
-            x0, w, dinv, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
-            [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
-              const TI y = ax * dio;
-              x1[idx] = y;
-              nn[0] += double(y) * double(y);
-              nn[1] += double(xown) * double(xown);
-            });
-      } else if constexpr (MG) {
-        for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) {
-          TI d;
-          const TI ax = apply_coarse(l, x0, idx, &d);
-          const TI y = ax / d;
-          x1[idx] = y;
-          nn[0] += double(y) * double(y);
-          nn[1] += double(x0[idx]) * double(x0[idx]);
-        }
-      }
+      staged<TI>(
+          l, x0, w, di, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+          [](TI a, TI ww) { return ww * a; },
+          [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
+            const TI y = ax * dio;
+            x1[idx] = y;
+            nn[0] += double(y) * double(y);
+            nn[1] += double(xown) * double(xown);
+          });
       tsum<2>(nn);
       lam = sqrt(nn[0] / nn[1]);
       const TI scl = TI(1.0 / sqrt(nn[0]));
-      if (l == 0) {
-        for (int q = threadIdx.x; q < nband(); q += BLOCK) {
-          const int idx = bidx(q);
-          x0[idx] = x1[idx] * scl;
-        }
-        sync();
-      } else {
-        for (int idx = threadIdx.x; idx < g.n; idx += BLOCK) x0[idx] = x1[idx] * scl;
-        __syncthreads();
+      for (int q = threadIdx.x; q < nb; q += BLOCK) {
+        const int idx = l == 0 ? bidx(q) : q;
+        x0[idx] = x1[idx] * scl;
       }
+      sync();
     }
     bytes = uni(bytes + (prm.power_iters * (5.0 * sizeof(TI) * g.n + dbytes(l))));
     return lam;
@@ -1117,6 +1072,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   double* __restrict__ uprev = reinterpret_cast<double*>(task.work + L->off_uprev);
   double* __restrict__ wk1 = reinterpret_cast<double*>(task.work + L->off_wk1);
   double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
+  double* __restrict__ dlt = reinterpret_cast<double*>(task.work + L->off_dlt);
   tm.V = reinterpret_cast<TI*>(task.work + L->off_V);
   tm.kdiag0 = reinterpret_cast<double*>(task.work + L->off_kd);
   tm.dinv = reinterpret_cast<TI*>(task.work + L->off_dinv);
@@ -1145,46 +1101,44 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     if (task.u_guess) W = task.u_guess + (int64_t)s * m * n0;
     else if (have_prev) W = prevU;
 
-    // ---- per-sample setup: coarse element tensors (averages of children; G == 1) ----
+    // ---- per-sample setup of the coarse V-cycle grids (one-workgroup teams):
+    // conductivity = mean of the element's 2^d children, stiffness diagonal
+    // from it and the grid's own fibre rows (rediscretisation) ----
     for (int l = 1; l < (MG ? L->nmg : 1); ++l) {
       const GridDev& gc = L->g[l];
       const GridDev& gf = L->g[l - 1];
-      TI* Dc = tm.mgD(l);
-      const TI* Df = tm.mgD(l - 1);
+      double* Sc = const_cast<double*>(tm.mgS(l));
+      const double* Sf = tm.mgS(l - 1);
       for (int e = tid; e < gc.ne; e += BLOCK) {
-        int E = e % gc.ex, F, Gz;
-        if constexpr (DIM == 2) {
-          F = e / gc.ex;
-          Gz = 0;
-        } else {
-          F = (e / gc.ex) % gc.ey;
-          Gz = e / (gc.ex * gc.ey);
-        }
-        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        const int E = e % gc.ex;
+        const int F = (DIM == 2) ? e / gc.ex : (e / gc.ex) % gc.ey;
+        const int Gz = (DIM == 2) ? 0 : e / (gc.ex * gc.ey);
+        double acc = 0.0;
         const int cz = (DIM == 3) ? 2 : 1;
         for (int c = 0; c < cz; ++c)
           for (int b = 0; b < 2; ++b)
             for (int a = 0; a < 2; ++a) {
               const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * Gz + c;
-              const int fe = (DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx);
-              if (l == 1) {
-                auto D = tensor_from<double, DIM>(tm.sigma[fe], L->fib + kFibStride * ((DIM == 3) ? fz : fy), tau, zr);
-                a0 += D.xx;
-                a1 += D.yy;
-                a3 += D.xy;
-                if constexpr (DIM == 3) a2 += D.zz;
-              } else {
-                a0 += Df[4 * fe];
-                a1 += Df[4 * fe + 1];
-                a2 += Df[4 * fe + 2];
-                a3 += Df[4 * fe + 3];
-              }
+              acc += Sf[(DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx)];
             }
-        const double inv = (l == 1 ? prm.theta : 1.0) / (4 * cz);  // theta K on every coarse grid
-        Dc[4 * e] = TI(a0 * inv);
-        Dc[4 * e + 1] = TI(a1 * inv);
-        Dc[4 * e + 2] = TI(a2 * inv);
-        Dc[4 * e + 3] = TI(a3 * inv);
+        Sc[e] = acc / (4 * cz);
+      }
+      __syncthreads();
+      double* Kc = tm.mgK(l);
+      const double* fibc = L->fib[l];
+      for (int idx = tid; idx < gc.n; idx += BLOCK) {
+        int i, j, k;
+        decode<DIM>(gc, idx, i, j, k);
+        auto z = [&](int, int, int) { return 0.0; };
+        double dd;
+        apply_at<double, DIM>(
+            gc, i, j, k, z, z,
+            [&](int ex, int ey, int ez) {
+              const int e = (DIM == 3) ? ((ez * gc.ey + ey) * gc.ex + ex) : (ey * gc.ex + ex);
+              return tensor_from<double, DIM>(Sc[e], fibc + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
+            },
+            0.0, &dd);
+        Kc[idx] = dd;
       }
       __syncthreads();
     }
@@ -1201,7 +1155,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           g0, i, j, k, z, z,
           [&](int ex, int ey, int ez) {
             const int e = (DIM == 3) ? ((ez * g0.ey + ey) * g0.ex + ex) : (ey * g0.ex + ex);
-            return tensor_from<double, DIM>(tm.sigma[e], L->fib + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
+            return tensor_from<double, DIM>(tm.sigma[e], L->fib[0] + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
           },
           0.0, &dd);
       tm.kdiag0[idx] = dd;
@@ -1212,8 +1166,14 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     }
     tm.sync();
 
-    long long newton_total = 0, krylov_total = 0;
+    long long newton_total = 0, krylov_total = 0, damped = 0;
     int newton_max_slab = 0, status = 0;
+    // bytes by the per-step word model: 4 float64 words per residual; per
+    // Krylov iteration j, 4 (Jacobian product) + the preconditioner's words
+    // (5 per sweep and per coarse-grid residual, weighted by the grid's nodes)
+    // + 2j + 3 (Arnoldi step) inner words, per node
+    double model_bytes = 0.0;
+    const double krylov_words = 7.0 + L->pc_words;
     double worst_final = 0.0;
     bool weights_ready = (prm.smoother == 0);
 
@@ -1237,6 +1197,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       int it = 0;
       bool conv = false;
       double dmax = 0.0;
+      // damping: the residual 2-norm of the last accepted iterate and the
+      // fraction of the last Newton step in u (halved while the residual grows)
+      double beta_acc = 0.0, tstep = 1.0;
       for (; it < prm.newton_max; ++it) {
         // ---- residual (float64) -> V_0, Jacobian weights on every grid ----
         TI* V0 = tm.V;
@@ -1249,7 +1212,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           TI* __restrict__ di = tm.dinv;
           const double cmd = (DIM == 3) ? 8.0 * g0.hx * g0.hy * g0.hz / 216.0 : 4.0 * g0.hx * g0.hy / 36.0;
           tm.template staged<double>(
-              u, uprev, tm.kdiag0, (const double*)nullptr,
+              0, u, uprev, tm.kdiag0, (const double*)nullptr,
               [th](double a, double b) { return th * a + (1.0 - th) * b; },
               [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
               [&](int idx, int i, int j, int k, double y, double uown, double, double kd, double) {
@@ -1257,25 +1220,32 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 const double w = inv_dt - react_d(uown, kr, ar);
                 V0[idx] = TI(r);
                 w0[idx] = TI(w);
-                di[idx] = TI(1.0 / (th * kd + tm.nel0(i, j, k) * cmd * w));
+                di[idx] = TI(1.0 / (th * kd + tm.nel(0, i, j, k) * cmd * w));
                 rr[0] += r * r;
               });
         }
         for (int l = 1; l < (MG ? L->nmg : 1); ++l) {  // G == 1 here
+          // reaction weights injected from grid 0, the coarse slab diagonal
           const GridDev& gc = L->g[l];
           TI* wl = tm.mgW(l);
+          TI* dl = tm.mgI(l);
+          const double* Kc = tm.mgK(l);
+          const double cmc = (DIM == 3) ? 8.0 * gc.hx * gc.hy * gc.hz / 216.0 : 4.0 * gc.hx * gc.hy / 36.0;
           const int st = 1 << l;
           for (int idx = tid; idx < gc.n; idx += BLOCK) {
             int I, J, K;
             decode<DIM>(gc, idx, I, J, K);
             const int q = (DIM == 3) ? (((K * st) * g0.ny + J * st) * g0.nx + I * st) : ((J * st) * g0.nx + I * st);
-            wl[idx] = TI(inv_dt - react_d(u[q], kr, ar));
+            const double w = inv_dt - react_d(u[q], kr, ar);
+            wl[idx] = TI(w);
+            dl[idx] = TI(1.0 / (th * Kc[idx] + tm.nel(l, I, J, K) * cmc * w));
           }
         }
         tm.template tsum<1>(rr);  // its barriers also publish the writes above
         STM_T1(t_res, 0);
+        model_bytes = uni(model_bytes + 32.0 * n0);
         const double beta = uni(sqrt(rr[0]));
-        if (!isfinite(beta)) {
+        if (!isfinite(beta) && !(prm.damping && it > 0 && tstep > kMinStep)) {
           status = -5;
           break;
         }
@@ -1284,6 +1254,23 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           dmax = 0.0;
           break;
         }
+        // the last step made the residual grow (or not finite): take half of
+        // it back, u -= (t/2) delta, and evaluate again (Armijo-style halving
+        // down to kMinStep; the pass counts as a Newton iteration)
+        if (prm.damping && it > 0 && !(beta <= beta_acc) && tstep > kMinStep) {
+          tstep = uni(0.5 * tstep);
+          for (int q = tid; q < nb; q += BLOCK) {
+            const int idx = tm.bidx(q);
+            u[idx] -= tstep * dlt[idx];
+          }
+          tm.bytes = uni(tm.bytes + 24.0 * n0);
+          dmax = uni(0.5 * dmax);
+          ++damped;
+          tm.sync();
+          continue;
+        }
+        beta_acc = beta;
+        tstep = 1.0;
         // ---- smoother weights: once per sample, from the first slab operator ----
         if (!weights_ready) {
           for (int l = 0; l < (MG ? L->nmg : 1); ++l) {
@@ -1309,6 +1296,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           TI* Vj = tm.V + j * vs;
           TI* Zj = tm.Z + j * vs;
           TI* Vn = tm.V + (j + 1) * vs;
+          model_bytes = uni(model_bytes + double(sizeof(TI)) * n0 * (krylov_words + 2.0 * j));
           STM_T0(t_vc);
           tm.vcycle(Vj, Zj);
           STM_T1(t_vc, 1);
@@ -1316,103 +1304,119 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           // pass A: ws = A Z_j (into V_{j+1})
           tm.bytes = uni(tm.bytes + (3.0 * sizeof(TI) * n0 + tm.dbytes(0)));
           tm.template staged<TI>(
-              Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+              0, Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
               [](TI a, TI ww) { return ww * a; },
               [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { Vn[idx] = w; });
           STM_T1(t_pa, 2);
-          STM_T0(t_dot);
-          // dots with V_0..V_min(j,7) over the owned nodes: batched loads
-          double d[9];
-#pragma unroll
-          for (int q = 0; q < 9; ++q) d[q] = 0.0;
-          const int nk0 = min(j + 1, 8);
-          tm.bytes = uni(tm.bytes + ((1.0 + nk0) * sizeof(TI) * n0));
-          {
-            const TI* __restrict__ Vb = tm.V;
-            const TI* __restrict__ Vr = Vn;
-            for (int qb = tid; qb < nb; qb += BLOCK * 2) {
-              TI wv[2], vv[2][8];
-#pragma unroll
-              for (int uu = 0; uu < 2; ++uu) {
-                const int q = qb + uu * BLOCK;
-                const int idx = q < nb ? tm.bidx(q) : 0;
-                wv[uu] = q < nb ? Vr[idx] : TI(0);
-#pragma unroll
-                for (int p = 0; p < 8; ++p) vv[uu][p] = (p < nk0 && q < nb) ? Vb[p * vs + idx] : TI(0);
-              }
-#pragma unroll
-              for (int uu = 0; uu < 2; ++uu)
-#pragma unroll
-                for (int p = 0; p < 8; ++p) d[p] += double(vv[uu][p]) * double(wv[uu]);
-            }
-          }
-          tm.template tsum<9>(d);
-          if (tid == 0) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-              if (q < nk0) H[q * kMaxRestart + j] = sc[q] * sc[j] * d[q];
-          }
-          for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
-            const int nk = min(j + 1 - k0, 8);
-            tm.bytes = uni(tm.bytes + ((1.0 + nk) * sizeof(TI) * n0));
+          // Classical Gram-Schmidt against V_0..V_j, done twice when the inner
+          // vectors are float32 (CGS2: the second pass restores the orthogonality
+          // the first loses to rounding); each pass adds its projections to
+          // column j of H.
+          double nn[1] = {0.0};
+          constexpr int kPasses = sizeof(TI) == 4 ? 2 : 1;
+#pragma unroll 1
+          for (int pass = 0; pass < kPasses; ++pass) {
+            STM_T0(t_dot);
+            // dots with V_0..V_min(j,7) over the owned nodes: batched loads
+            double d[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) d[q] = 0.0;
-            for (int q = tid; q < nb; q += BLOCK) {
-              const int idx = tm.bidx(q);
-              const double wd = double(Vn[idx]);
+            const int nk0 = min(j + 1, 8);
+            tm.bytes = uni(tm.bytes + ((1.0 + nk0) * sizeof(TI) * n0));
+            {
+              const TI* __restrict__ Vb = tm.V;
+              const TI* __restrict__ Vr = Vn;
+              for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+                TI wv[2], vv[2][8];
 #pragma unroll
-              for (int p = 0; p < 8; ++p)
-                if (p < nk) d[p] += double(tm.V[(k0 + p) * vs + idx]) * wd;
+                for (int uu = 0; uu < 2; ++uu) {
+                  const int q = qb + uu * BLOCK;
+                  const int idx = q < nb ? tm.bidx(q) : 0;
+                  wv[uu] = q < nb ? Vr[idx] : TI(0);
+#pragma unroll
+                  for (int p = 0; p < 8; ++p) vv[uu][p] = (p < nk0 && q < nb) ? Vb[p * vs + idx] : TI(0);
+                }
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu)
+#pragma unroll
+                  for (int p = 0; p < 8; ++p) d[p] += double(vv[uu][p]) * double(wv[uu]);
+              }
             }
             tm.template tsum<9>(d);
             if (tid == 0) {
 #pragma unroll
               for (int q = 0; q < 8; ++q)
-                if (q < nk) H[(k0 + q) * kMaxRestart + j] = sc[k0 + q] * sc[j] * d[q];
+                if (q < nk0) coef[q] = d[q];
             }
-          }
-          if (tid == 0)
-            for (int q = 0; q <= j; ++q) coef[q] = H[q * kMaxRestart + j] * sc[q] / sc[j];
-          __syncthreads();
-          STM_T1(t_dot, 3);
-          STM_T0(t_pb);
-          // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
-          double nn[1] = {0.0};
-          tm.bytes = uni(tm.bytes + ((j + 3.0) * sizeof(TI) * n0));
-          // vectors in chunks of 4, all loads of a chunk issued before use
-          for (int qb = tid; qb < nb; qb += BLOCK * 2) {
-            double w[2];
-            int ix[2];
+            for (int k0 = 8; k0 <= j; k0 += 8) {  // remaining dot chunks
+              const int nk = min(j + 1 - k0, 8);
+              tm.bytes = uni(tm.bytes + ((1.0 + nk) * sizeof(TI) * n0));
 #pragma unroll
-            for (int uu = 0; uu < 2; ++uu) {
-              const int q = qb + uu * BLOCK;
-              ix[uu] = q < nb ? tm.bidx(q) : 0;
-              w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
-            }
-            for (int q0 = 0; q0 <= j; q0 += 4) {
-              TI vv[4][2];
+              for (int q = 0; q < 9; ++q) d[q] = 0.0;
+              for (int q = tid; q < nb; q += BLOCK) {
+                const int idx = tm.bidx(q);
+                const double wd = double(Vn[idx]);
 #pragma unroll
-              for (int p = 0; p < 4; ++p)
+                for (int p = 0; p < 8; ++p)
+                  if (p < nk) d[p] += double(tm.V[(k0 + p) * vs + idx]) * wd;
+              }
+              tm.template tsum<9>(d);
+              if (tid == 0) {
 #pragma unroll
-                for (int uu = 0; uu < 2; ++uu)
-                  vv[p][uu] = (q0 + p <= j) ? tm.V[(q0 + p) * vs + ix[uu]] : TI(0);
-#pragma unroll
-              for (int p = 0; p < 4; ++p) {
-                const double cq = (q0 + p <= j) ? coef[q0 + p] : 0.0;
-#pragma unroll
-                for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[p][uu]);
+                for (int q = 0; q < 8; ++q)
+                  if (q < nk) coef[k0 + q] = d[q];
               }
             }
+            // projections onto the normalised basis enter H; V_q is stored with
+            // norm 1/sc[q], so w loses (sc[q]^2 <V_q, w>) V_q
+            if (tid == 0)
+              for (int q = 0; q <= j; ++q) {
+                const double hq = sc[q] * sc[j] * coef[q];
+                H[q * kMaxRestart + j] = (pass ? H[q * kMaxRestart + j] : 0.0) + hq;
+                coef[q] = sc[q] * sc[q] * coef[q];
+              }
+            __syncthreads();
+            STM_T1(t_dot, 3);
+            STM_T0(t_pb);
+            // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
+            nn[0] = 0.0;
+            tm.bytes = uni(tm.bytes + ((j + 3.0) * sizeof(TI) * n0));
+            // vectors in chunks of 4, all loads of a chunk issued before use
+            for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+              double w[2];
+              int ix[2];
 #pragma unroll
-            for (int uu = 0; uu < 2; ++uu) {
-              if (qb + uu * BLOCK < nb) {
-                const TI wt = TI(w[uu]);
-                Vn[ix[uu]] = wt;
-                nn[0] += double(wt) * double(wt);
+              for (int uu = 0; uu < 2; ++uu) {
+                const int q = qb + uu * BLOCK;
+                ix[uu] = q < nb ? tm.bidx(q) : 0;
+                w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
+              }
+              for (int q0 = 0; q0 <= j; q0 += 4) {
+                TI vv[4][2];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                  for (int uu = 0; uu < 2; ++uu)
+                    vv[p][uu] = (q0 + p <= j) ? tm.V[(q0 + p) * vs + ix[uu]] : TI(0);
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                  const double cq = (q0 + p <= j) ? coef[q0 + p] : 0.0;
+#pragma unroll
+                  for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[p][uu]);
+                }
+              }
+#pragma unroll
+              for (int uu = 0; uu < 2; ++uu) {
+                if (qb + uu * BLOCK < nb) {
+                  const TI wt = TI(w[uu]);
+                  Vn[ix[uu]] = wt;
+                  nn[0] += double(wt) * double(wt);
+                }
               }
             }
+            tm.template tsum<1>(nn);  // its barriers also publish V_{j+1}
+            STM_T1(t_pb, 4);
           }
-          tm.template tsum<1>(nn);
           const double hn = uni(sqrt(nn[0]));
           if (tid == 0) {
             const double hj1 = sc[j] * hn;
@@ -1434,7 +1438,6 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             sh_resid = fabs(gv[j + 1]);
           }
           __syncthreads();
-          STM_T1(t_pb, 4);
           jdim = j + 1;
           const double resid = uni(sh_resid);
           if (!(resid > tol_abs) || !(hn > 0.0)) break;
@@ -1452,9 +1455,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
         // ---- u += sum_q y_q z_q (float64) over the owned nodes, max-norm of the step ----
         STM_T0(t_up);
         double dm = 0.0;
-        tm.bytes = uni(tm.bytes + (double(jdim) * sizeof(TI) * n0 + 16.0 * n0));
+        tm.bytes = uni(tm.bytes + (double(jdim) * sizeof(TI) * n0 + 24.0 * n0));
         for (int qb = tid; qb < nb; qb += BLOCK * 2) {
-          double dlt[2] = {0.0, 0.0}, uo[2];
+          double dl[2] = {0.0, 0.0}, uo[2];
           int ix[2];
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
@@ -1472,14 +1475,15 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             for (int p = 0; p < 4; ++p) {
               const double cq = (q0 + p < jdim) ? coef[q0 + p] : 0.0;
 #pragma unroll
-              for (int v = 0; v < 2; ++v) dlt[v] += cq * double(zz[p][v]);
+              for (int v = 0; v < 2; ++v) dl[v] += cq * double(zz[p][v]);
             }
           }
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
             if (qb + v * BLOCK < nb) {
-              u[ix[v]] = uo[v] + dlt[v];
-              dm = fmax(dm, fabs(dlt[v]));
+              u[ix[v]] = uo[v] + dl[v];
+              dlt[ix[v]] = dl[v];
+              dm = fmax(dm, fabs(dl[v]));
             }
           }
         }
@@ -1548,8 +1552,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
       st.final_step = worst_final;
       st.ticks = wall_clock64() - t_start;
       st.censored = (int)cen[0];
-      st.pad = 0;
+      st.damped = (int)damped;
       st.alg_bytes = tm.bytes;
+      st.model_bytes = model_bytes;
       for (int q = 0; q < 8; ++q) st.phase_ticks[q] = 0;
 #ifdef STM_PHASE_TIMERS
       for (int q = 0; q < 8; ++q) st.phase_ticks[q] = ph_acc[q];
@@ -1579,11 +1584,12 @@ static const void* kernel_for_block(int block) {
   }
 }
 
-// The multi-grid kernel variant (MG = true) is not built: the library rejects
-// problems with more than one V-cycle grid.
+// The multi-grid kernel variant (MG = true) serves launches with a level
+// whose V-cycle has coarse grids; the others take the single-grid variant,
+// which compiles none of the coarse-grid code.
 template <int DIM>
 static const void* kernel_for_dim(bool fp32, bool mg, int block) {
-  if (mg) return nullptr;
+  if (mg) return fp32 ? kernel_for_block<float, DIM, true>(block) : kernel_for_block<double, DIM, true>(block);
   return fp32 ? kernel_for_block<float, DIM, false>(block) : kernel_for_block<double, DIM, false>(block);
 }
 

@@ -21,7 +21,7 @@ struct LevelHost {
   LevelDev dev;          // host copy (device pointers inside)
   int64_t team_bytes;    // workspace per team without the space-time buffer
   int64_t u_bytes;       // space-time buffer m * n0 float64
-  double* fib = nullptr; // device fibre table
+  double* fib[kMaxMG] = {}; // device fibre table of every grid
   double* u0 = nullptr;  // device initial state at the nodes of grid 0
 };
 
@@ -151,15 +151,14 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
   if (p.coarse_sweeps < 0 || p.coarse_sweeps > kMaxSweeps || p.smooth_steps < 0 || p.smooth_steps > kMaxSweeps)
     return fail(c, STM_E_INVALID, "sweep counts must be in 0..32");
   if (p.smoother < 0 || p.smoother > 1) return fail(c, STM_E_INVALID, "smoother must be 0 or 1");
-  if (p.mg_levels != 0 && p.mg_levels != 1)
-    return fail(c, STM_E_UNSUPPORTED,
-                "mg_levels other than 1 is disabled: the multi-grid V-cycle kernel faulted once on the GPU "
-                "with no cause found yet; the single-grid preconditioner is the supported path");
+  if (p.mg_levels < -1 || p.mg_levels > kMaxMG)
+    return fail(c, STM_E_INVALID, "mg_levels must be -1 (deepest), 0 (default 1) or 1 .. 8");
   if (p.field_kind != STM_FIELD_LOGNORMAL && p.field_kind != STM_FIELD_ADDITIVE)
     return fail(c, STM_E_INVALID, "field_kind must be 0 (lognormal) or 1 (additive)");
   if (p.tau_relative != 0 && p.tau_relative != 1) return fail(c, STM_E_INVALID, "tau_relative must be 0 or 1");
   if (p.ic_kind != STM_IC_BALL && p.ic_kind != STM_IC_GAUSS) return fail(c, STM_E_INVALID, "ic_kind must be 0 or 1");
   if (p.qoi != STM_QOI_ACTIVATION && p.qoi != STM_QOI_SPACETIME) return fail(c, STM_E_INVALID, "qoi must be 0 or 1");
+  if (p.newton_damping < -1 || p.newton_damping > 1) return fail(c, STM_E_INVALID, "newton_damping must be -1, 0 or 1");
   if (!(p.ic_radius >= 0)) return fail(c, STM_E_INVALID, "ic_radius must be >= 0");
   if (p.ic_kind == STM_IC_GAUSS && !(p.ic_radius > 0))
     return fail(c, STM_E_INVALID, "the Gaussian initial state needs ic_radius > 0");
@@ -175,7 +174,7 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too small");
     if (L.smooth_sweeps < 0 || L.smooth_sweeps > kMaxSweeps || !(L.cheb_ratio == 0 || L.cheb_ratio > 1))
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": smooth_sweeps in 0..32, cheb_ratio 0 or > 1");
-    for (int g = 0; g < 16; ++g)
+    for (int g = 0; g < 32; ++g)
       if (!(L.team_seconds[g] >= 0 && std::isfinite(L.team_seconds[g])))
         return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": team_seconds must be finite and >= 0");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
@@ -209,9 +208,12 @@ void fill_defaults(stm_problem& p) {
   if (p.max_lanes <= 0) p.max_lanes = 1024;
 }
 
-int auto_block(const stm_problem& p, int n0) {
+// Threads per solver workgroup.  Launches of the multi-grid variant take
+// 256: with four waves per workgroup the 3D variant may use up to 512
+// registers per lane and needs no scratch memory.
+int auto_block(const stm_problem& p, int n0, bool mg) {
   if (p.block_threads) return p.block_threads;
-  if (n0 <= 2500) return 256;
+  if (mg || n0 <= 2500) return 256;
   return 512;
 }
 
@@ -242,29 +244,32 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   d.sweeps = lv.smooth_sweeps > 0 ? lv.smooth_sweeps : p.coarse_sweeps;
   d.cheb_ratio = lv.cheb_ratio > 0 ? lv.cheb_ratio : p.cheb_ratio;
 
-  // fibre table per element row (2D) / layer (3D)
+  // fibre table of every grid, per element row (2D) / layer (3D) at that grid's centroids
   const GridDev& g0 = d.g[0];
-  const int rows = p.dim == 2 ? g0.ey : g0.ez;
-  std::vector<double> fib(kFibStride * rows);
   const double ratio = p.transverse_ratio;
-  for (int r = 0; r < rows; ++r) {
-    const double yc = (r + 0.5) * g0.hy, zc = (r + 0.5) * g0.hz;
-    const double th = p.dim == 2 ? fiber_angle(p, yc, 0.0) : fiber_angle(p, 0.0, zc);
-    const double cth = std::cos(th), sth = std::sin(th);
-    double* f = fib.data() + kFibStride * r;
-    if (p.tau_relative) {  // tau_e = ratio sigma_e
-      f[0] = cth * cth + ratio * sth * sth;
-      f[1] = sth * sth + ratio * cth * cth;
-      f[2] = (1.0 - ratio) * cth * sth;
-    } else {  // tau = ratio sigma_f0
-      f[0] = cth * cth;
-      f[1] = sth * sth;
-      f[2] = cth * sth;
+  for (int k = 0; k < nmg; ++k) {
+    const GridDev& g = d.g[k];
+    const int rows = p.dim == 2 ? g.ey : g.ez;
+    std::vector<double> fib(kFibStride * rows);
+    for (int r = 0; r < rows; ++r) {
+      const double yc = (r + 0.5) * g.hy, zc = (r + 0.5) * g.hz;
+      const double th = p.dim == 2 ? fiber_angle(p, yc, 0.0) : fiber_angle(p, 0.0, zc);
+      const double cth = std::cos(th), sth = std::sin(th);
+      double* f = fib.data() + kFibStride * r;
+      if (p.tau_relative) {  // tau_e = ratio sigma_e
+        f[0] = cth * cth + ratio * sth * sth;
+        f[1] = sth * sth + ratio * cth * cth;
+        f[2] = (1.0 - ratio) * cth * sth;
+      } else {  // tau = ratio sigma_f0
+        f[0] = cth * cth;
+        f[1] = sth * sth;
+        f[2] = cth * sth;
+      }
     }
+    STM_HIP(c, hipMalloc(&out.fib[k], fib.size() * sizeof(double)));
+    STM_HIP(c, hipMemcpy(out.fib[k], fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice));
+    d.fib[k] = out.fib[k];
   }
-  STM_HIP(c, hipMalloc(&out.fib, fib.size() * sizeof(double)));
-  STM_HIP(c, hipMemcpy(out.fib, fib.data(), fib.size() * sizeof(double), hipMemcpyHostToDevice));
-  d.fib = out.fib;
   {
     // initial state at the nodes of grid 0: the ball or the Gaussian bump
     const GridDev& g = d.g[0];
@@ -297,6 +302,7 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   d.off_V = take(ti * vs * (R + 1));
   d.off_Z = take(ti * vs * R);
   d.off_kd = take(8 * (size_t)n0);
+  d.off_dlt = take(8 * (size_t)n0);
   d.off_dinv = take(ti * n0);
   for (int k = 0; k < nmg; ++k) {
     const GridDev& g = d.g[k];
@@ -305,41 +311,59 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
     if (k > 0) {
       d.off_mgX[k] = take(ti * g.n);
       d.off_mgB[k] = take(ti * g.n);
-      d.off_mgD[k] = take(ti * 4 * (size_t)g.ne);
+      d.off_mgI[k] = take(ti * g.n);
+      d.off_mgS[k] = take(8 * (size_t)g.ne);
+      d.off_mgK[k] = take(8 * (size_t)g.n);
     }
+  }
+  // words per grid-0 node of one preconditioner application: smoothing sweeps
+  // (5 words each) and, above the coarsest grid, the residual (5 words as a
+  // sweep), each on grid k weighted by its nodes
+  {
+    const int nu = p.smooth_steps;
+    double w = 0.0;
+    for (int k = 0; k < nmg; ++k) {
+      const double frac = (double)d.g[k].n / g0.n;
+      w += frac * 5.0 * (k + 1 < nmg ? 2 * nu + 1 : d.sweeps);
+    }
+    d.pc_words = w;
   }
   out.team_bytes = (int64_t)off;
   d.off_U = off;
   // LDS tiles: maximise interior / staged nodes within the staging budget,
   // per field size and number of staged nodal fields (2 to 4)
   const size_t budget = (size_t)c->stage_bytes;
-  for (int es = 0; es < 2; ++es) {
-    const size_t fb = es == 0 ? 8 : 4;
-    for (int nfl = 2; nfl <= 4; ++nfl) {
-      int by = 1, bz = 1;
-      double best = -1.0;
-      const int zmax = p.dim == 3 ? g0.nz : 1;
-      for (int rz = 1; rz <= zmax; ++rz) {
-        for (int ry = 1; ry <= g0.ny; ++ry) {
-          const int sy = std::min(ry + 2, g0.ny), sz = p.dim == 3 ? std::min(rz + 2, g0.nz) : 1;
-          const int ey = std::min(ry + 1, g0.ey), ez = p.dim == 3 ? std::min(rz + 1, g0.ez) : 1;
-          const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
-          // staged nodal fields, element conductivities, element
-          // contributions, fibre rows of the tile
-          const size_t bytes = nfl * fb * (size_t)sy * sz * g0.nx + 16 + (8 + fb * nv) * (size_t)ey * ez * g0.ex +
-                               16 + 8 * kFibStride * (size_t)(p.dim == 2 ? ey : ez);
-          if (bytes > budget) break;
-          const double eff = (double)std::min(ry, g0.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
-          if (eff > best) {
-            best = eff;
-            by = ry;
-            bz = rz;
+  for (int k = 0; k < nmg; ++k) {
+    const GridDev& gk = d.g[k];
+    for (int es = 0; es < 2; ++es) {
+      const size_t fb = es == 0 ? 8 : 4;
+      for (int nfl = 2; nfl <= 4; ++nfl) {
+        int by = 1, bz = 1;
+        double best = -1.0;
+        const int zmax = p.dim == 3 ? gk.nz : 1;
+        for (int rz = 1; rz <= zmax; ++rz) {
+          for (int ry = 1; ry <= gk.ny; ++ry) {
+            const int sy = std::min(ry + 2, gk.ny), sz = p.dim == 3 ? std::min(rz + 2, gk.nz) : 1;
+            const int ey = std::min(ry + 1, gk.ey), ez = p.dim == 3 ? std::min(rz + 1, gk.ez) : 1;
+            const size_t nv = p.dim == 3 ? 8 : 4;  // per-element vertex contributions
+            // staged nodal fields, element conductivities, element
+            // contributions, fibre rows of the tile
+            const size_t bytes = nfl * fb * (size_t)sy * sz * gk.nx + 16 +
+                                 (8 + fb * nv) * (size_t)ey * ez * gk.ex + 16 +
+                                 8 * kFibStride * (size_t)(p.dim == 2 ? ey : ez);
+            if (bytes > budget) break;
+            const double eff = (double)std::min(ry, gk.ny) * std::min(rz, zmax) / ((double)sy * sz) + 1e-6 * ry * rz;
+            if (eff > best) {
+              best = eff;
+              by = ry;
+              bz = rz;
+            }
           }
         }
+        if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
+        d.tile_y[k][es][nfl - 2] = by;
+        d.tile_z[k][es][nfl - 2] = bz;
       }
-      if (best < 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
-      d.tile_y[es][nfl - 2] = by;
-      d.tile_z[es][nfl - 2] = bz;
     }
   }
   // fused two-sweep smoother pass (2D): five nodal fields over the tile's rows
@@ -385,7 +409,22 @@ stm_status timed_end(stm_ctx* c, double* acc_ms) {
 // (synchronous).  Members of a team with G > 1 are placed on workgroup
 // indices of one residue class mod 8, so that with round-robin dispatch over
 // the 8 XCDs a team shares one L2; correctness does not depend on it.
-stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
+// Device bytes of a launch's team synchronisation area: barrier counters (one
+// 128-byte line per team), reduction partials and the fault flag.
+size_t sync_bytes_for(size_t n_teams, int max_g) {
+  return n_teams * 32 * 4 + n_teams * 2 * (size_t)max_g * 16 * 8 + 256;
+}
+
+// Caller-provided device areas for run_tasks (the allocation-free entry point);
+// null members mean the context's growable buffers.
+struct FixedAreas {
+  unsigned char* sync = nullptr;
+  size_t sync_cap = 0;
+  TeamTask* tasks = nullptr;
+  size_t tasks_cap = 0;
+};
+
+stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block, const FixedAreas* fixed = nullptr) {
   if (teams.empty()) return STM_OK;
   int n_blocks = 0, n_multi = 0, max_g = 1;
   for (auto& t : teams) {
@@ -394,15 +433,22 @@ stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
     max_g = std::max(max_g, t.G);
   }
   const bool coop = max_g > 1;
-  // barrier counters (one 128-byte line per team) + partials + fault flag
   const size_t ctr_words = (size_t)teams.size() * 32;
   const size_t part_doubles = (size_t)teams.size() * 2 * max_g * 16;
-  const size_t sync_bytes = ctr_words * 4 + part_doubles * 8 + 256;
-  stm_status st = grow(c, &c->d_sync, &c->sync_cap, sync_bytes);
-  if (st != STM_OK) return st;
-  unsigned* ctr = reinterpret_cast<unsigned*>(c->d_sync);
-  double* part = reinterpret_cast<double*>(c->d_sync + ctr_words * 4);
-  int* fault = reinterpret_cast<int*>(c->d_sync + ctr_words * 4 + part_doubles * 8);
+  const size_t sync_bytes = sync_bytes_for(teams.size(), max_g);
+  stm_status st = STM_OK;
+  unsigned char* sync = nullptr;
+  if (fixed) {
+    if (sync_bytes > fixed->sync_cap || (size_t)n_blocks * sizeof(TeamTask) > fixed->tasks_cap)
+      return fail(c, STM_E_INVALID, "launch tables exceed the fixed scratch areas");
+    sync = fixed->sync;
+  } else {
+    if ((st = grow(c, &c->d_sync, &c->sync_cap, sync_bytes))) return st;
+    sync = c->d_sync;
+  }
+  unsigned* ctr = reinterpret_cast<unsigned*>(sync);
+  double* part = reinterpret_cast<double*>(sync + ctr_words * 4);
+  int* fault = reinterpret_cast<int*>(sync + ctr_words * 4 + part_doubles * 8);
   // placement: free slots per residue class
   std::vector<std::vector<int>> cls(8);
   for (int b = n_blocks - 1; b >= 0; --b) cls[b % 8].push_back(b);
@@ -450,13 +496,19 @@ stm_status run_tasks(stm_ctx* c, std::vector<TeamTask>& teams, int block) {
     blocks[b].fault = fault;
   }
   (void)n_multi;
-  if ((st = grow(c, &c->d_tasks, &c->tasks_cap, blocks.size() * sizeof(TeamTask)))) return st;
-  STM_HIP(c, hipMemcpyAsync(c->d_tasks, blocks.data(), blocks.size() * sizeof(TeamTask), hipMemcpyHostToDevice,
+  TeamTask* d_tasks = nullptr;
+  if (fixed) {
+    d_tasks = fixed->tasks;
+  } else {
+    if ((st = grow(c, &c->d_tasks, &c->tasks_cap, blocks.size() * sizeof(TeamTask)))) return st;
+    d_tasks = c->d_tasks;
+  }
+  STM_HIP(c, hipMemcpyAsync(d_tasks, blocks.data(), blocks.size() * sizeof(TeamTask), hipMemcpyHostToDevice,
                             c->stream));
   hipError_t e = launch_fill_u32(ctr, 0u, (int64_t)(sync_bytes / 4), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "fill");
   if ((st = timed_begin(c))) return st;
-  e = launch_team_solver(c->p.dim, c->inner_fp32, c->any_mg, c->d_levels, c->d_tasks, n_blocks, c->prm, block,
+  e = launch_team_solver(c->p.dim, c->inner_fp32, c->any_mg, c->d_levels, d_tasks, n_blocks, c->prm, block,
                          (size_t)c->stage_bytes, coop, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, coop ? "cooperative team solver launch" : "team solver launch");
   // the task table stays alive until the kernel has finished
@@ -486,6 +538,7 @@ int block_capacity(stm_ctx* c, int block) {
 }
 
 void reset_timings(stm_ctx* c) { c->tm = stm_timings{}; }
+
 
 }  // namespace
 
@@ -560,8 +613,9 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
   s.coarse_sweeps = c->p.coarse_sweeps;
   s.smoother = (c->p.smoother == 1) ? 0 : 1;  // kernel: 1 = Chebyshev weights, 0 = fixed
   s.cheb_ratio = c->p.cheb_ratio;
-  s.power_iters = 10;
+  s.power_iters = 40;
   s.theta = c->p.theta;
+  s.damping = c->p.newton_damping >= 0 ? 1 : 0;
   *out = c;
   return STM_OK;
 }
@@ -570,7 +624,8 @@ void stm_destroy(stm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (auto& l : c->levels) {
-    if (l.fib) (void)hipFree(l.fib);
+    for (double* f : l.fib)
+      if (f) (void)hipFree(f);
     if (l.u0) (void)hipFree(l.u0);
   }
   if (c->d_levels) (void)hipFree(c->d_levels);
@@ -623,8 +678,13 @@ stm_status stm_kl_synthesize(stm_ctx* c, int level, const double* modes, const d
   return timed_end(c, &c->tm.kl_ms);
 }
 
-stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
-                        stm_solve_stats* stats_host) {
+}  // extern "C"
+
+namespace {
+
+// stm_st_solve.
+stm_status st_solve_impl(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
+                         stm_solve_stats* stats_host) {
   if (!c) return STM_E_INVALID;
   c->err.clear();
   if (level < 0 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level out of range");
@@ -633,15 +693,21 @@ stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double
   stm_status st;
   if ((st = check_ptr(c, sigma, "sigma")) || (st = check_ptr(c, u, "u"))) return st;
   LevelHost& L = c->levels[level];
-  const int block = auto_block(c->p, L.dev.g[0].n);
+  const int block = auto_block(c->p, L.dev.g[0].n, c->any_mg);
   const int cap = std::min(c->p.max_lanes, block_capacity(c, block));
   // few samples: several workgroups per sample (up to the level's limit)
   int G = 1;
   if (c->p.team_size > 0) G = std::min(c->p.team_size, max_team(c, level));
   else if (S * 2 <= cap) G = std::min(max_team(c, level), std::max(1, cap / S));
-  const int lanes = std::max(1, std::min(S, cap / G));
-  if ((st = grow(c, &c->work, &c->work_bytes, (size_t)lanes * L.team_bytes))) return st;
-  if ((st = grow(c, &c->d_stats, &c->stats_cap, (size_t)S * sizeof(SampleStatsDev)))) return st;
+  int lanes = std::max(1, std::min(S, cap / G));
+  unsigned char* work = nullptr;
+  SampleStatsDev* d_stats = nullptr;
+  {
+    if ((st = grow(c, &c->work, &c->work_bytes, (size_t)lanes * L.team_bytes))) return st;
+    if ((st = grow(c, &c->d_stats, &c->stats_cap, (size_t)S * sizeof(SampleStatsDev)))) return st;
+    work = static_cast<unsigned char*>(c->work);
+    d_stats = c->d_stats;
+  }
   std::vector<TeamTask> tasks(lanes);
   for (int i = 0; i < lanes; ++i) {
     TeamTask& t = tasks[i];
@@ -654,33 +720,49 @@ stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double
     t.u_out = u;
     t.u_guess = u0_guess;
     t.t_act = nullptr;
-    t.work = static_cast<unsigned char*>(c->work) + (size_t)i * L.team_bytes;
-    t.stats = c->d_stats;
+    t.work = work + (size_t)i * L.team_bytes;
+    t.stats = d_stats;
     t.G = G;
   }
   reset_timings(c);
   if ((st = run_tasks(c, tasks, block))) return st;
-  std::vector<SampleStatsDev> sd(S);
-  STM_HIP(c, hipMemcpy(sd.data(), c->d_stats, S * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
   int worst = 0;
-  for (int s = 0; s < S; ++s) {
-    if (sd[s].status < worst) worst = sd[s].status;
-    c->tm.solve_bytes += sd[s].alg_bytes;
-    if (stats_host) {
-      stm_solve_stats& o = stats_host[s];
-      o.status = sd[s].status;
-      o.newton_max_per_slab = sd[s].newton_max_per_slab;
-      o.newton_iters = sd[s].newton_iters;
-      o.krylov_iters = sd[s].krylov_iters;
-      o.final_step = sd[s].final_step;
-      o.device_seconds = sd[s].ticks * 1e-8;
-      o.algorithmic_bytes = sd[s].alg_bytes;
-      for (int q = 0; q < 8; ++q) o.phase_seconds[q] = sd[s].phase_ticks[q] * 1e-8;
+  SampleStatsDev sd[64];
+  for (int s0 = 0; s0 < S; s0 += 64) {
+    const int ns = std::min(64, S - s0);
+    STM_HIP(c, hipMemcpy(sd, d_stats + s0, ns * sizeof(SampleStatsDev), hipMemcpyDeviceToHost));
+    for (int q = 0; q < ns; ++q) {
+      const int s = s0 + q;
+      if (sd[q].status < worst) worst = sd[q].status;
+      c->tm.solve_bytes += sd[q].alg_bytes;
+      c->tm.solve_bytes_model += sd[q].model_bytes;
+      if (stats_host) {
+        stm_solve_stats& o = stats_host[s];
+        o.status = sd[q].status;
+        o.newton_max_per_slab = sd[q].newton_max_per_slab;
+        o.newton_iters = sd[q].newton_iters;
+        o.krylov_iters = sd[q].krylov_iters;
+        o.final_step = sd[q].final_step;
+        o.device_seconds = sd[q].ticks * 1e-8;
+        o.algorithmic_bytes = sd[q].alg_bytes;
+        o.model_bytes = sd[q].model_bytes;
+        o.damped_steps = sd[q].damped;
+        for (int k = 0; k < 8; ++k) o.phase_seconds[k] = sd[q].phase_ticks[k] * 1e-8;
+      }
     }
   }
   if (worst == STM_E_NONFINITE) return fail(c, STM_E_NONFINITE, "non-finite residual in a sample");
   if (worst == STM_E_NOT_CONVERGED) return fail(c, STM_E_NOT_CONVERGED, "Newton iteration limit reached in a sample");
   return STM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
+                        stm_solve_stats* stats_host) {
+  return st_solve_impl(c, level, sigma, u0_guess, S, u, stats_host);
 }
 
 stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, double* t_act, int* n_censored_host) {
@@ -1004,7 +1086,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
                                 c->stream));
     }
     int block = 256;
-    for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n));
+    for (auto& g : gs) block = std::max(block, auto_block(c->p, c->levels[g.grid].dev.g[0].n, c->any_mg));
     allocate_lanes(gs, std::min(lane_budget, block_capacity(c, block)));
     size_t ws = 0;
     for (auto& g : gs) ws += (size_t)g.lanes * (c->levels[g.grid].team_bytes + c->levels[g.grid].u_bytes);
@@ -1170,6 +1252,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
   out->krylov_iters = 0;
   out->censored = 0;
   out->algorithmic_bytes = 0.0;
+  out->model_bytes = 0.0;
   out->dof_steps = 0;
   for (int l = 0; l < L1; ++l) {
     out->N[l] = Ndone[l];
@@ -1183,6 +1266,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
         out->krylov_iters += s.krylov_iters;
         out->censored += s.censored;
         out->algorithmic_bytes += s.alg_bytes;
+        out->model_bytes += s.model_bytes;
         worst = std::min(worst, s.status);
       }
       const LevelDev& dg = c->levels[cm ? l - 1 : l].dev;
@@ -1197,6 +1281,7 @@ extern "C" stm_status stm_mlmc_estimate(stm_ctx* c, const int* N_host, const dou
   }
   out->worst_status = worst;
   c->tm.solve_bytes = out->algorithmic_bytes;
+  c->tm.solve_bytes_model = out->model_bytes;
   if (worst == STM_E_NONFINITE) return fail(c, STM_E_NONFINITE, "non-finite residual in a sample");
   if (worst == STM_E_NOT_CONVERGED) return fail(c, STM_E_NOT_CONVERGED, "Newton iteration limit reached in a sample");
   return STM_OK;

@@ -10,7 +10,7 @@ namespace stm {
 constexpr int kMaxMG = 8;        // multigrid grids per MLMC level
 constexpr int kMaxRestart = 30;  // Krylov dimension limit
 constexpr int kWave = 64;
-constexpr int kMaxTeam = 16;  // largest team of workgroups per sample
+constexpr int kMaxTeam = 32;  // largest team of workgroups per sample
 
 // One structured grid: nodes per axis, elements per axis, spacing.
 struct GridDev {
@@ -40,22 +40,30 @@ struct LevelDev {
   double dt, T;
   int nmg;                      // multigrid grids (>= 1)
   int sweeps;                   // Jacobi sweeps on the coarsest V-cycle grid
+  double pc_words;              // words per grid-0 node that one preconditioner application moves
+                                // (per-step model: 5 per sweep and per residual, on each grid
+                                // weighted by its nodes)
   double cheb_ratio;            // Chebyshev interval ratio of the sweep weights
   GridDev g[kMaxMG];
-  const double* fib;            // grid-0 fibre table: per element row (2D) / layer (3D): c^2, s^2, c s
+  const double* fib[kMaxMG];    // fibre table of every grid: per element row (2D) / layer (3D): c^2, s^2, c s
+                                // at that grid's own element centroids
   const double* u0;     // initial state at the nodes of grid 0 (filled by the host)
   // team workspace layout (bytes from the team base)
   int64_t off_u, off_uprev, off_wk1, off_tact;          // float64 [n0]
   int64_t off_V, off_Z;                                 // inner [restart+1][n0], [restart][n0]
   int64_t off_kd;                                       // float64 [n0] stiffness diagonal of grid 0
+  int64_t off_dlt;                                      // float64 [n0] last Newton step (damping)
   int64_t off_dinv;                                     // inner [n0] inverse diagonal of the slab operator
   int64_t off_mgX[kMaxMG], off_mgT[kMaxMG], off_mgB[kMaxMG], off_mgW[kMaxMG];  // inner [n_l]
-  int64_t off_mgD[kMaxMG];                              // inner [ne_l][4] element tensors (l >= 1)
+  int64_t off_mgI[kMaxMG];                              // inner [n_l] inverse slab diagonal (l >= 1)
+  int64_t off_mgS[kMaxMG];                              // float64 [ne_l] conductivity: mean of children (l >= 1)
+  int64_t off_mgK[kMaxMG];                              // float64 [n_l] stiffness diagonal (l >= 1)
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
   int64_t team_bytes;
-  // LDS tiles of grid-0 stencil passes: node rows (y) and planes (z) per
-  // tile, [8-byte (0) or 4-byte (1) fields][2, 3 or 4 staged nodal fields]
-  int tile_y[2][3], tile_z[2][3];
+  // LDS tiles of the stencil passes on every grid: node rows (y) and planes
+  // (z) per tile, [grid][8-byte (0) or 4-byte (1) fields][2, 3 or 4 staged
+  // nodal fields]
+  int tile_y[kMaxMG][2][3], tile_z[kMaxMG][2][3];
   // node rows per tile of the fused two-sweep smoother pass (2D), for 8-byte
   // and 4-byte inner vectors
   int tile_p8, tile_p4;
@@ -78,6 +86,7 @@ struct SolverParams {
   double cheb_ratio;
   int power_iters;      // power iterations estimating lmax(D^-1 A) per sample and grid
   double theta;         // weight of the new time level in the diffusion term (1: BE, 1/2: CN)
+  int damping;          // 1: halve a Newton step while the residual grows; 0: full steps
 };
 
 constexpr int kMaxSweeps = 32;
@@ -118,9 +127,10 @@ struct SampleStatsDev {
   double final_step;
   long long ticks;           // wall-clock ticks (100 MHz) spent on the sample
   int censored;
-  int pad;
+  int damped;                // Newton steps halved because the residual grew
   double alg_bytes;          // bytes the sample's passes must move (per-pass model)
   long long phase_ticks[8];  // per-phase wall-clock ticks when built with STM_PHASE_TIMERS, else 0
+  double model_bytes;        // bytes by the per-step word model (see stm_solve_stats)
 };
 
 // ---------------------------------------------------------------------------

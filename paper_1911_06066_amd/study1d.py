@@ -24,7 +24,8 @@ def main():
     ap.add_argument("--workload", default="cable1d")
     ap.add_argument("--reference", type=int, default=20000)
     ap.add_argument("--repeats", type=int, default=8)
-    ap.add_argument("--levels", type=int, default=0, help="finest level to study (default: all)")
+    ap.add_argument("--levels", type=int, default=0,
+                    help="number of levels to study (default: all); the reference is always MC on the finest")
     a = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import torch
@@ -36,7 +37,8 @@ def main():
     if wl.get("qoi") != "spacetime":
         raise SystemExit("the study needs a workload with the space-time QoI")
     dev = torch.device("cuda:0")
-    Lmax = (a.levels or len(wl["levels"])) - 1
+    Lmax = len(wl["levels"]) - 1  # the reference level
+    Lstudy = (a.levels or len(wl["levels"])) - 1
     modes_all = [torch.from_numpy(m).to(dev) for m in klmodes.workload_modes(wl)]
     M = wl["n_modes"]
 
@@ -77,7 +79,7 @@ def main():
     # reference: plain MC on the finest level
     vref, wref = estimate(Lmax, [a.reference], 99991, True)
     print(json.dumps({"reference": {"level": Lmax, "samples": a.reference, "work_s": wref}}), flush=True)
-    for L in range(Lmax + 1):
+    for L in range(Lstudy + 1):
         # the reference restricted to level L's space-time points: nested in space and time
         nxL, nyL = wl["levels"][L]
         nxF, nyF = wl["levels"][Lmax]

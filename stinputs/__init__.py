@@ -17,8 +17,8 @@ grid whose element counts are 64 x 64 x 16 etc.):
                 (ell 0.15, s2 0.2), 256 samples, mixed precision
   mlmc5_3d      five 3D levels 9x9x3 ... 129x129x33 nodes, 32 ... 512 steps,
                 128 modes, sample counts chosen adaptively
-  cable1d       the 1D+1 hierarchy of Table 1 as a strip of one element row:
-                31 2^l elements of 0.032 / 2^l cm, 4 2^l steps of 0.16 / 2^l ms,
+  cable1d       the 1D+1 hierarchy of Table 1 (all six levels) as a strip of one
+                element row: 31 2^l elements of 0.032 / 2^l cm, 4 2^l steps of 0.16 / 2^l ms,
                 the cube's physics and field, space-time QoI E[u]
   cube4_3d      the paper's cube: [0,1]^3 cm, 6^3 ... 41^3 nodes, 24 ... 192
                 steps to 0.96 ms, isotropic additive uniform field (Gaussian
@@ -117,10 +117,13 @@ WORKLOADS = {
                          samples=[1024, 256, 64, 16], precision="mixed"),
     "slab3d": _w(_COMMON_3D, name="slab3d", levels=[(65, 65, 17)], steps=[256],
                  n_modes=64, samples=[256], precision="mixed"),
+    # adaptive counts: pilot samples per level, then the optimal allocation
+    # for an RMSE of target_rmse * T, up to `capacity` samples per level.  One
+    # finest sample costs about 90 workgroup-seconds, so the pilot is 8
     "mlmc5_3d": _w(_COMMON_3D, name="mlmc5_3d",
                    levels=[(9, 9, 3), (17, 17, 5), (33, 33, 9), (65, 65, 17), (129, 129, 33)],
                    steps=[32, 64, 128, 256, 512], n_modes=128, samples=None,
-                   target_rmse=1e-3, pilot=32, precision="mixed"),
+                   target_rmse=1e-3, pilot=8, capacity=[2048, 1024, 512, 128, 32], precision="mixed"),
     "cube4_3d": _w(_CUBE_3D, name="cube4_3d",
                    levels=[(6, 6, 6), (11, 11, 11), (21, 21, 21), (41, 41, 41)],
                    steps=[24, 48, 96, 192], n_modes=66, kl_grid=(41, 41, 41),
@@ -134,8 +137,9 @@ WORKLOADS = {
     # the stochastic heat equation: no ionic current (k_react = 0)
     "cable1d": _w(_CUBE_3D, name="cable1d", dim=2, lengths=(0.992, 0.002), T=0.64, k_react=0.0,
                   ic_center=(0.0, 0.001), ic_radius=0.25,
-                  levels=[(32, 2), (63, 2), (125, 2), (249, 2)], steps=[4, 8, 16, 32],
-                  n_modes=16, kl_grid=(249, 2), samples=[4096, 256, 16, 2], qoi="spacetime",
+                  levels=[(32, 2), (63, 2), (125, 2), (249, 2), (497, 2), (993, 2)],
+                  steps=[4, 8, 16, 32, 64, 128],
+                  n_modes=16, kl_grid=(249, 2), samples=[4096, 256, 16, 2, 2, 2], qoi="spacetime",
                   precision="fp64"),
 }
 

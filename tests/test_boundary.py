@@ -60,7 +60,8 @@ def _c_layout(struct, fields):
 
 
 @pytest.mark.parametrize("cname,pyname", [("stm_problem", "StmProblem"), ("stm_solve_stats", "StmSolveStats"),
-                                          ("stm_mlmc_result", "StmMlmcResult"), ("stm_level", "StmLevel")])
+                                          ("stm_mlmc_result", "StmMlmcResult"), ("stm_level", "StmLevel"),
+                                          ("stm_timings", "StmTimings")])
 def test_struct_layouts_match_header(cname, pyname):
     L, _ = _lib()
     cls = getattr(L, pyname)
@@ -94,13 +95,14 @@ def test_gaussian_initial_state_needs_a_radius():
     assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
 
 
-def test_multigrid_variant_is_refused():
-    """More than one V-cycle grid is rejected as unsupported (-6), not run."""
+@pytest.mark.parametrize("mg_levels", [-2, 9])
+def test_multigrid_depth_out_of_range_rejected(mg_levels):
+    """V-cycle depths outside -1 (deepest) .. 8 grids are invalid arguments."""
     L, lib = _lib()
     from paper_1911_06066_amd import problem_from_workload
-    p = problem_from_workload(stinputs.workload("small_mc_2d"), mg_levels=-1)
+    p = problem_from_workload(stinputs.workload("small_mc_2d"), mg_levels=mg_levels)
     h = ctypes.c_void_p()
-    assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -6 and not h.value
+    assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
 
 
 def test_non_nested_levels_rejected():

@@ -218,6 +218,32 @@ def test_nonconvergence_is_reported_not_hidden(torch_dev):
     assert e.value.code == "STM_E_NOT_CONVERGED"
 
 
+@pytest.mark.parametrize("shape,m,precision", [((17, 17), 8, "fp64"), ((17, 17), 4, "fp64"), ((33, 33), 8, "fp64"),
+                                               ((33, 33), 8, "mixed"), ((17, 17), 4, "mixed")])
+def test_large_time_steps_converge_like_the_oracle(torch_dev, shape, m, precision):
+    """dt = T/8 and T/4: the slab Newton takes large steps from the previous
+    slab (halved while the residual grows, as the oracle's) and reaches the
+    oracle's solution, which converges there."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = _wl(levels=[shape], steps=[m], precision=precision)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    U_ref, st_ref = oapi.st_solve(wl, 0, sig, mode="timestep")
+    assert all(s.converged for s in st_ref)
+    ctx = Context(wl)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    t, _ = ctx.activation_map(0, u)
+    t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+    if precision == "fp64":
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+    else:
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-8
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-6 * wl["T"]
+
+
 def test_activation_map_kernel_vs_oracle_on_synthetic_series(torch_dev):
     torch, dev = torch_dev
     from paper_1911_06066_amd import Context
@@ -250,6 +276,38 @@ def test_st_solve_3d_fp64_matches_oracle(torch_dev):
     t, cen = ctx.activation_map(0, u)
     t_ref, _ = oapi.activation_map(wl, 0, U_ref)
     assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+
+
+@pytest.mark.parametrize("shape,precision,G", [((9, 9, 9), "fp64", 1), ((9, 9, 9), "mixed", 3),
+                                               ((17, 17, 9), "fp64", 1), ((17, 17, 9), "fp64", 3),
+                                               ((17, 17, 9), "mixed", 1), ((17, 17, 9), "mixed", 3)])
+def test_rot3d_fibres_on_many_z_tiles_match_oracle(torch_dev, shape, precision, G):
+    """The fibre angle changes with every element layer (rot3d).  A 16 KiB
+    staging budget cuts the 9 node planes into tiles of one or two planes, so
+    every staged pass (2, 3 and 4 staged fields) reads its fibre rows at a
+    per-tile layer offset; teams of 3 add row bands."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("slab3d", levels=[shape], steps=[6], n_modes=8, kl_grid=(9, 9, 3),
+                           precision=precision, ic_radius=0.3, sigma_f0=4e-3)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    ctx = Context(wl, lds_kb=16, team_size=G)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    assert ctx.timings()["solve_blocks"] == G * ctx.timings()["solve_teams"]
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    t, _ = ctx.activation_map(0, u)
+    t_ref, _ = oapi.activation_map(wl, 0, U_ref)
+    if precision == "fp64":
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
+    else:
+        assert _rel(u.cpu().numpy(), U_ref) < 1e-8
+        assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-6 * wl["T"]
+    # the law matters at this size: fibres along x give a different solution
+    U_x, _ = oapi.st_solve(dict(wl, fiber_law="x"), 0, sig, mode="timestep")
+    assert _rel(U_x, U_ref) > 1e-6
 
 
 # ---------------------------------------------------------------------------

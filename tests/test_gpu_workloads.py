@@ -221,8 +221,10 @@ def test_adaptive_sample_counts_follow_the_allocation_rule(torch_dev):
     assert np.abs(out["mean"].cpu().numpy() - lm.sum(axis=0)).max() <= 1e-12 * T
 
 
-@pytest.mark.skip(reason="the multi-grid kernel variant faulted the GPU once (memory aperture violation) "
-                         "with no cause found by reading the code; mg_levels > 1 is rejected until it is")
+@pytest.mark.skip(reason="written for the earlier multi-grid kernel variant (coarse grids read from global "
+                         "memory, the solver state in scratch memory), which faulted the GPU once (memory aperture "
+                         "violation) with no cause shown; that variant was removed, and the V-cycle rebuilt on the "
+                         "staged LDS passes is covered by tests/test_gpu_multigrid.py")
 @pytest.mark.parametrize("dim", [2, 3])
 def test_multigrid_vcycle_matches_oracle(torch_dev, dim):
     """The multigrid preconditioner (restriction, coarse operators from
@@ -245,3 +247,65 @@ def test_multigrid_vcycle_matches_oracle(torch_dev, dim):
     assert all(s["status"] == 0 for s in stats), stats
     U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
     assert _rel(u.cpu().numpy(), U_ref) < 1e-9
+
+
+def _read_prefix_golden(path):
+    norms, sums, nodes, vals = {}, {}, [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            p = line.split()
+            if p[0] == "norm2":
+                norms[int(p[1])] = float(p[2])
+            elif p[0] == "sum":
+                sums[int(p[1])] = float(p[2])
+            elif p[0] == "node":
+                nodes.append(int(p[1]))
+                vals.append([float(v) for v in p[2:]])
+    return norms, sums, np.array(nodes), np.array(vals)
+
+
+@pytest.mark.parametrize("precision,G", [("fp64", 16), ("mixed", 1), ("mixed", 16)])
+def test_slab3d_full_size_prefix_matches_stored_oracle(torch_dev, precision, G):
+    """The full 65 x 65 x 17 slab, 256 steps, rotating fibres: its first two
+    slabs against the oracle's (tests/golden/slab3d_prefix2.txt, written by
+    make_slab3d_prefix.py from the oracle alone; minutes of sparse LU per slab):
+    the 2-norm and sum over all nodes and the values at 1.3k nodes around the
+    stimulus and 300 others.  The solve takes the conductivity stored with
+    them: the covariance's degenerate eigenpairs make modes computed on another
+    machine a different, equally valid basis.  One workgroup per sample as in
+    the slab workload, and a team of 16 as for the finest 3D MLMC levels."""
+    import os
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    gdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    norms, sums, nodes, vals = _read_prefix_golden(os.path.join(gdir, "slab3d_prefix2.txt"))
+    sig = np.load(os.path.join(gdir, "slab3d_prefix2_sigma.npy"))[None]
+    wl = stinputs.workload("slab3d", precision=precision)
+    ctx = Context(wl, level_tuning=_tuning(wl), team_size=G)
+    u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+    assert all(s["status"] == 0 for s in stats), stats
+    assert ctx.timings()["solve_blocks"] == G
+    up = u[0, :2].cpu().numpy()
+    ctx.close()
+    tol = 1e-9 if precision == "fp64" else 1e-8
+    for k in (1, 2):
+        assert abs(np.linalg.norm(up[k - 1]) - norms[k]) <= tol * norms[k]
+        # the sum adds 71825 nodal errors of either sign: ten times the bound
+        assert abs(up[k - 1].sum() - sums[k]) <= 10 * tol * abs(sums[k])
+    assert _rel(up[:, nodes].T, vals) < tol
+
+
+def test_slab3d_full_size_kl_synthesis_matches_oracle(torch_dev):
+    """The float64 KL GEMM at the slab's full size (65536 elements, 64 modes)
+    against the oracle's synthesis from the same modes."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("slab3d", precision="fp64")
+    basis = oapi.kl_basis(wl)
+    modes = oapi.kl_modes(wl, 0, basis)
+    xi = stinputs.xi("slab3d", 0, 4, wl["n_modes"])
+    with Context(wl) as ctx:
+        sig = ctx.kl_synthesize(0, torch.from_numpy(modes).to(dev), torch.from_numpy(xi).to(dev))
+    assert _rel(sig.cpu().numpy(), oapi.kl_synthesize(modes, xi, wl["sigma_f0"])) < 1e-14
