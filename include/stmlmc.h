@@ -276,6 +276,24 @@ stm_status stm_st_solve(stm_ctx* ctx, int level, const double* sigma, const doub
                         int S, double* u, stm_solve_stats* stats_host);
 
 /*
+ * stm_st_solve without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * stm_st_solve.  Every device area the call needs beyond the caller's arrays
+ * (team synchronisation, the launch's task table, per-sample statistics, the
+ * team workspaces) lives in one fixed array of 64 MiB per device, held from
+ * the first stm_create on that device until the process ends; the call takes
+ * fewer concurrent lanes when the workspaces of all would not fit, and
+ * returns STM_E_INVALID, before any work is enqueued, when the statistics of
+ * S samples and one lane's workspace exceed it.  The array is shared by every
+ * call on the device and keeps the last call's contents (the call clears what
+ * must start at zero): calls that overlap on one device, from any context or
+ * stream, race.
+ */
+stm_status stm_st_solve_noalloc(stm_ctx* ctx, int level, const double* sigma, const double* u0_guess,
+                                int S, double* u, stm_solve_stats* stats_host);
+
+/*
  * Activation map of S space-time solutions u[S][m][n] on `level`:
  * t_act[s][i] = 0 if u_0 >= threshold, else the first up-crossing of the
  * threshold, linear in t between the bracketing time levels, else T

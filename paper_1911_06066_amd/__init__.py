@@ -167,7 +167,9 @@ class Context:
         self._raise(self.lib.stm_kl_synthesize(self.h, level, _ptr(modes), _ptr(xi), S, _ptr(out)))
         return out
 
-    def st_solve(self, level, sigma, u0_guess=None, out=None, stats=True):
+    def st_solve(self, level, sigma, u0_guess=None, out=None, stats=True, noalloc=False):
+        """noalloc: through stm_st_solve_noalloc (the library allocates no device
+        memory; pass `out` to allocate none here either)."""
         torch = _torch()
         n, E, m = self.sizes[level]
         S = sigma.shape[0]
@@ -178,8 +180,8 @@ class Context:
             out = torch.empty((S, m, n), dtype=torch.float64, device=sigma.device)
         _check_dev(out, "u", torch.float64, (S, m, n))
         st_arr = (_lib.StmSolveStats * max(S, 1))() if stats else None
-        st = self.lib.stm_st_solve(self.h, level, _ptr(sigma), _ptr(u0_guess), S, _ptr(out),
-                                   st_arr if stats else None)
+        fn = self.lib.stm_st_solve_noalloc if noalloc else self.lib.stm_st_solve
+        st = fn(self.h, level, _ptr(sigma), _ptr(u0_guess), S, _ptr(out), st_arr if stats else None)
         self._raise(st)
         if not stats:
             return out, None

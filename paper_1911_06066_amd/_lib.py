@@ -114,6 +114,8 @@ SIGNATURES = {
     "stm_kl_synthesize": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P]),
     "stm_st_solve": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P,
                                     ctypes.POINTER(StmSolveStats)]),
+    "stm_st_solve_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P,
+                                            ctypes.POINTER(StmSolveStats)]),
     "stm_activation_map": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P,
                                           ctypes.POINTER(ctypes.c_int)]),
     "stm_prolong_st": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int, _P]),

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,7 @@ struct stm_ctx {
   // runs one sample per team, so that its slowest sample decides its end too
   double tail_ratio[STM_MAX_LEVELS] = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
   int stage_bytes = 48 * 1024;   // dynamic LDS per solver workgroup
+  void* scratch_dev = nullptr;   // device address of this device's no-allocation scratch array
 };
 
 namespace {
@@ -539,6 +541,7 @@ int block_capacity(stm_ctx* c, int block) {
 
 void reset_timings(stm_ctx* c) { c->tm = stm_timings{}; }
 
+void* device_scratch(int device);
 
 }  // namespace
 
@@ -587,6 +590,9 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
     c->any_mg = c->any_mg || c->levels[l].dev.nmg > 1;
     for (int g = 1; g <= kMaxTeam; ++g) c->tsec[l][g] = std::max(0.0, c->p.levels[l].team_seconds[g - 1]);
   }
+  // this device's no-allocation scratch array (stm_st_solve_noalloc); resolved
+  // here, with the device current, once per device
+  c->scratch_dev = device_scratch(c->device);
   if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
     stm_destroy(c);
     return STM_E_DEVICE;
@@ -680,11 +686,41 @@ stm_status stm_kl_synthesize(stm_ctx* c, int level, const double* modes, const d
 
 }  // extern "C"
 
+// The no-allocation area (see stm_st_solve_noalloc): one per device, resolved
+// once per device with the device current.  In host code the array's name is
+// only a stand-in for the symbol; its device address comes from
+// hipGetSymbolAddress and is the only one used.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
-// stm_st_solve.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (null on error).
+void* device_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+// stm_st_solve and stm_st_solve_noalloc.  With noalloc every device area the
+// launch needs beyond the caller's arrays -- team synchronisation, the task
+// table, per-sample statistics and the team workspaces -- is carved from the
+// device's scratch array (fewer lanes if the workspaces do not all fit), and
+// no device memory is allocated.
 stm_status st_solve_impl(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
-                         stm_solve_stats* stats_host) {
+                         stm_solve_stats* stats_host, bool noalloc) {
   if (!c) return STM_E_INVALID;
   c->err.clear();
   if (level < 0 || level >= c->p.n_levels) return fail(c, STM_E_INVALID, "level out of range");
@@ -702,7 +738,32 @@ stm_status st_solve_impl(stm_ctx* c, int level, const double* sigma, const doubl
   int lanes = std::max(1, std::min(S, cap / G));
   unsigned char* work = nullptr;
   SampleStatsDev* d_stats = nullptr;
-  {
+  FixedAreas areas;
+  if (noalloc) {
+    unsigned char* base = static_cast<unsigned char*>(c->scratch_dev);
+    if (!base) return fail(c, STM_E_DEVICE, "the no-allocation scratch array of this device is not available");
+    const size_t stats_bytes = align_up((size_t)S * sizeof(SampleStatsDev));
+    auto need = [&](int ln) {
+      return align_up(sync_bytes_for((size_t)ln, G)) + align_up((size_t)ln * G * sizeof(TeamTask)) + stats_bytes +
+             (size_t)ln * (size_t)L.team_bytes;
+    };
+    while (lanes > 1 && need(lanes) > kNoAllocBytes) --lanes;
+    if (need(lanes) > kNoAllocBytes)
+      return fail(c, STM_E_INVALID,
+                  "stm_st_solve_noalloc needs " + std::to_string(need(lanes)) + " bytes of scratch for " +
+                      std::to_string(S) + " samples on level " + std::to_string(level) + "; the array holds " +
+                      std::to_string(kNoAllocBytes));
+    size_t off = 0;
+    areas.sync = base + off;
+    areas.sync_cap = align_up(sync_bytes_for((size_t)lanes, G));
+    off += areas.sync_cap;
+    areas.tasks = reinterpret_cast<TeamTask*>(base + off);
+    areas.tasks_cap = align_up((size_t)lanes * G * sizeof(TeamTask));
+    off += areas.tasks_cap;
+    d_stats = reinterpret_cast<SampleStatsDev*>(base + off);
+    off += stats_bytes;
+    work = base + off;
+  } else {
     if ((st = grow(c, &c->work, &c->work_bytes, (size_t)lanes * L.team_bytes))) return st;
     if ((st = grow(c, &c->d_stats, &c->stats_cap, (size_t)S * sizeof(SampleStatsDev)))) return st;
     work = static_cast<unsigned char*>(c->work);
@@ -725,7 +786,7 @@ stm_status st_solve_impl(stm_ctx* c, int level, const double* sigma, const doubl
     t.G = G;
   }
   reset_timings(c);
-  if ((st = run_tasks(c, tasks, block))) return st;
+  if ((st = run_tasks(c, tasks, block, noalloc ? &areas : nullptr))) return st;
   int worst = 0;
   SampleStatsDev sd[64];
   for (int s0 = 0; s0 < S; s0 += 64) {
@@ -762,7 +823,12 @@ extern "C" {
 
 stm_status stm_st_solve(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S, double* u,
                         stm_solve_stats* stats_host) {
-  return st_solve_impl(c, level, sigma, u0_guess, S, u, stats_host);
+  return st_solve_impl(c, level, sigma, u0_guess, S, u, stats_host, false);
+}
+
+stm_status stm_st_solve_noalloc(stm_ctx* c, int level, const double* sigma, const double* u0_guess, int S,
+                                double* u, stm_solve_stats* stats_host) {
+  return st_solve_impl(c, level, sigma, u0_guess, S, u, stats_host, true);
 }
 
 stm_status stm_activation_map(stm_ctx* c, int level, const double* u, int S, double* t_act, int* n_censored_host) {
