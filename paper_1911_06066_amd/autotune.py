@@ -280,7 +280,9 @@ def main():
     if a.teams_only >= 0:
         precision = a.precision or wl.get("precision", "fp64")
         path = tuning_path(wl["name"], precision)
-        with open(path) as f:
+        # an existing output file accumulates the tables of several runs
+        src = a.out if a.out and os.path.exists(a.out) else path
+        with open(src) as f:
             rec = json.load(f)
         measure_teams(wl, rec, a.teams_only, log=lambda s: print(s, flush=True))
         out = a.out or path

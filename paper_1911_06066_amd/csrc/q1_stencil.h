@@ -179,51 +179,85 @@ __device__ __forceinline__ void elem_apply_2d(const T (&k)[4], const T (&m)[4], 
   out[3] = p1 + q1 + A + B + cm * (T(2) * r11 + r01);
 }
 
-// 1D factor [[2,1],[1,2]] along one axis of a 2x2x2 block given by index stride
+// The 3D element: with vertex v = bx + 2 by + 4 bz and s = 2 b - 1 per axis,
+//   (K_e k)_v = s_x A(by, bz) + s_y B(bx, bz) + s_z C(bx, by)
+//   A = ax [M_y M_z dx] + axy [M_z hy],  B = ay [M_x M_z dy] + axy [M_z hx],
+//   C = az [M_x M_y dz],
+//   (M_e m)_v = cm [M_x M_y M_z m]_v
+// where dx(by, bz) are the four x-edge differences of k (likewise dy, dz),
+// hx(bz), hy(bz) the sums of a z-layer's two x- resp. y-edge differences, and
+// M = [[2, 1], [1, 2]] along the named axis; ax = D_xx h_y h_z / (36 h_x),
+// ay, az likewise, axy = D_xy h_z / 24, cm = h_x h_y h_z / 216 (an element
+// with a constant tensor whose fibres lie in the x-y plane).  Only the unique
+// factors are formed, which keeps few values live.
 template <typename T>
-__device__ __forceinline__ void m1_axis(T (&f)[8], int stride) {
+__device__ __forceinline__ void m1_pair(T& a, T& b) {
+  const T x = a, y = b;
+  a = T(2) * x + y;
+  b = x + T(2) * y;
+}
+
+template <typename T>
+__device__ __forceinline__ void elem_apply_3d(const T (&k)[8], const T (&m)[8], T ax, T ay, T az, T axy, T cm,
+                                              T (&out)[8]) {
+  // edge differences: index (the two other axes' bits) = first + 2 second
+  T dx[4], dy[4], dz[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int b1 = u & 1, b2 = u >> 1;
+    dx[u] = k[1 + 2 * b1 + 4 * b2] - k[2 * b1 + 4 * b2];  // (by, bz)
+    dy[u] = k[b1 + 2 + 4 * b2] - k[b1 + 4 * b2];          // (bx, bz)
+    dz[u] = k[b1 + 2 * b2 + 4] - k[b1 + 2 * b2];          // (bx, by)
+  }
+  T hx[2] = {dx[0] + dx[1], dx[2] + dx[3]};  // per bz
+  T hy[2] = {dy[0] + dy[1], dy[2] + dy[3]};
+  m1_pair(hx[0], hx[1]);
+  m1_pair(hy[0], hy[1]);
+  // M along both other axes of each difference set
+  m1_pair(dx[0], dx[1]);
+  m1_pair(dx[2], dx[3]);
+  m1_pair(dx[0], dx[2]);
+  m1_pair(dx[1], dx[3]);
+  m1_pair(dy[0], dy[1]);
+  m1_pair(dy[2], dy[3]);
+  m1_pair(dy[0], dy[2]);
+  m1_pair(dy[1], dy[3]);
+  m1_pair(dz[0], dz[1]);
+  m1_pair(dz[2], dz[3]);
+  m1_pair(dz[0], dz[2]);
+  m1_pair(dz[1], dz[3]);
+  T fm[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) fm[v] = m[v];
+#pragma unroll
+  for (int v = 0; v < 8; v += 2) m1_pair(fm[v], fm[v + 1]);
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    if (!(v & 2)) m1_pair(fm[v], fm[v + 2]);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) m1_pair(fm[v], fm[v + 4]);
+  T A[4], B[4], C[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    A[u] = ax * dx[u] + axy * hy[u >> 1];
+    B[u] = ay * dy[u] + axy * hx[u >> 1];
+    C[u] = az * dz[u];
+  }
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    if (v & stride) continue;
-    const T a = f[v], b = f[v + stride];
-    f[v] = T(2) * a + b;
-    f[v + stride] = a + T(2) * b;
+    const int bx = v & 1, by = (v >> 1) & 1, bz = v >> 2;
+    const T a = A[by + 2 * bz], b = B[bx + 2 * bz], c = C[bx + 2 * by];
+    T acc = bx ? a : -a;
+    acc += by ? b : -b;
+    acc += bz ? c : -c;
+    out[v] = acc + cm * fm[v];
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void elem_apply_3d(const T (&k)[8], const T (&m)[8], const Tensor3<T>& D, T cxx, T cyy,
                                               T czz, T cxy, T cm, T (&out)[8]) {
-  T fx[8], fy[8], fz[8], fm[8], gxy[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    // s_a (f1 - f0) along each axis
-    const int bx = v & 1, by = (v >> 1) & 1, bz = (v >> 2) & 1;
-    const T dxv = k[v | 1] - k[v & ~1];
-    const T dyv = k[v | 2] - k[v & ~2];
-    const T dzv = k[v | 4] - k[v & ~4];
-    fx[v] = bx ? dxv : -dxv;
-    fy[v] = by ? dyv : -dyv;
-    fz[v] = bz ? dzv : -dzv;
-    fm[v] = m[v];
-  }
-  // xy coupling: s_vx (h_y(0) + h_y(1)) + s_vy (h_x(0) + h_x(1)), h = differences
-#pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    const int bx = v & 1, by = (v >> 1) & 1;
-    const int base = v & 4;  // same z layer
-    const T hy = (k[base | 2] - k[base]) + (k[base | 3] - k[base | 1]);
-    const T hx = (k[base | 1] - k[base]) + (k[base | 3] - k[base | 2]);
-    gxy[v] = (bx ? hy : -hy) + (by ? hx : -hx);
-  }
-  m1_axis(fx, 2); m1_axis(fx, 4);
-  m1_axis(fy, 1); m1_axis(fy, 4);
-  m1_axis(fz, 1); m1_axis(fz, 2);
-  m1_axis(gxy, 4);
-  m1_axis(fm, 1); m1_axis(fm, 2); m1_axis(fm, 4);
-  const T ax = D.xx * cxx, ay = D.yy * cyy, az = D.zz * czz, axy = D.xy * cxy;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) out[v] = ax * fx[v] + ay * fy[v] + az * fz[v] + axy * gxy[v] + cm * fm[v];
+  elem_apply_3d<T>(k, m, D.xx * cxx, D.yy * cyy, D.zz * czz, D.xy * cxy, cm, out);
 }
 
 }  // namespace stm

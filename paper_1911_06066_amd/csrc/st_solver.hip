@@ -62,6 +62,27 @@ __device__ __forceinline__ double uni(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// Global-memory views of generic pointers.  An access through a generic
+// pointer that the compiler cannot place compiles to a flat instruction, and
+// flat instructions count against the LDS wait counter as well: every LDS wait
+// of a pass would then also wait for the pass's global loads and stores in
+// flight.  Device arrays are global; these views make their accesses global
+// (cmem: read-only tables, loaded through the scalar cache when uniform).
+#define STM_GLOBAL __attribute__((address_space(1)))
+#define STM_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ STM_GLOBAL T* gmem(T* p) {
+  return (STM_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const STM_GLOBAL T* gmem(const T* p) {
+  return (const STM_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const STM_CONST T* cmem(const T* p) {
+  return (const STM_CONST T*)p;
+}
+
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
 constexpr double kMinStep = 1.0 / 64;  // smallest damped fraction of a Newton step
 constexpr unsigned kSpinLimit = 1u << 25;
@@ -280,6 +301,259 @@ struct Team {
   template <typename T, typename KV, typename MV, typename Body>
   __device__ __forceinline__ void staged(int l, const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
                          const T* __restrict__ f3, KV kval, MV mval, Body body) const {
+    if constexpr (DIM == 3) {
+      zmarch<T>(l, f0, f1, f2, f3, kval, mval, body);
+    } else {
+      staged_tiles<T>(l, f0, f1, f2, f3, kval, mval, body);
+    }
+  }
+
+  // ---- z-marching pass (3D) -------------------------------------------------
+  // The owned rows of grid l are cut into y-tiles of Ry rows over the whole x
+  // extent, and each tile marches through the planes k = 0 .. nz-1.  LDS holds
+  // a ring of three planes of f0, f1 over the tile's rows plus a one-row halo,
+  // four partial sums per element of one element layer, and per-thread areas:
+  // the top-face contributions of the thread's elements of the previous layer,
+  // their conductivities and f2, f3 at the thread's output nodes.  Element q of
+  // a layer and output node q of a plane always belong to thread q % BLOCK, so
+  // those areas need no barrier.  Step k:
+  //   * issue the loads of plane k+2 of f0, f1, of the conductivities of
+  //     element layer k+1 and of f2, f3 on plane k+1 (into registers);
+  //   * phase A: the vertex contributions of the thread's elements of layer k
+  //     (between planes k and k+1) by sum factorisation; bottom-face ones plus
+  //     the stored top-face ones of layer k-1 are the four sums the element
+  //     gives plane k (to LDS); the new top-face ones replace the stored ones;
+  //   * phase B: every output node of plane k adds the sums of the four
+  //     elements around it in its plane and calls body;
+  //   * the loaded values go to LDS (their latency overlapped both phases).
+  // f0 and f1 are read from memory once per tile (plus the halo rows), f2, f3
+  // and the conductivities once; two workgroup barriers per plane.  Ends with
+  // a team barrier.
+  template <typename T, typename KV, typename MV, typename Body>
+  __device__ __forceinline__ void zmarch(int l, const T* __restrict__ f0, const T* __restrict__ f1,
+                                         const T* __restrict__ f2, const T* __restrict__ f3, KV kval, MV mval,
+                                         Body body) const {
+    constexpr int CE = 4;  // elements of a layer per thread
+    constexpr int CN = 5;  // staged nodes of a plane per thread
+    constexpr int CB = 4;  // output nodes of a plane per thread
+    const GridDev& g = L->g[l];
+    const int nx = g.nx, ny = g.ny, nz = g.nz, EX = g.ex, EY = g.ey, EZ = g.ez;
+    const unsigned mnx = g.mnx, mex = g.mex;
+    const int plane = ny * nx, eplane = EY * EX;
+    // tile rows: the LDS budget (set on the host) and the per-thread counts
+    const int jb0 = l == 0 ? this->jb0 : 0, jb1 = l == 0 ? this->jb1 : ny;
+    const int Rmax = max(1, min((int)L->tile_y[l][sizeof(T) == 8 ? 0 : 1][0],
+                                min(CE * BLOCK / EX - 1, min(CN * BLOCK / nx - 2, CB * BLOCK / nx))));
+    // as few tiles as Rmax allows, of equal height
+    const int ntl = (jb1 - jb0 + Rmax - 1) / Rmax;
+    const int Ry = (jb1 - jb0 + ntl - 1) / max(ntl, 1);
+    const STM_GLOBAL double* __restrict__ sg = gmem(mgS(l));
+    const STM_CONST double* __restrict__ fib = cmem(L->fib[l]);
+    const STM_GLOBAL T* __restrict__ g0 = gmem(f0);
+    const STM_GLOBAL T* __restrict__ g1 = gmem(f1);
+    const STM_GLOBAL T* __restrict__ g2 = gmem(f2);
+    const STM_GLOBAL T* __restrict__ g3 = gmem(f3);
+    const double tau = prm.tau, zr = prm.zr;
+    const T hx = T(g.hx), hy = T(g.hy), hz = T(g.hz);
+    const T cxx = hy * hz / (T(36) * hx), cyy = hx * hz / (T(36) * hy), czz = hx * hy / (T(36) * hz);
+    const T cxy = hz / T(24), cm = hx * hy * hz / T(216);
+    const int tid = threadIdx.x;
+    T* __restrict__ P = reinterpret_cast<T*>(smem);
+    for (int j0 = jb0; j0 < jb1; j0 += Ry) {
+      const int je = min(j0 + Ry, jb1);          // output rows [j0, je)
+      const int jr0 = max(j0 - 1, 0);            // staged node rows [jr0, jr1]; element rows start there too
+      const int jr1 = min(je, ny - 1);
+      const int ey1 = min(je - 1, EY - 1);       // element rows [jr0, ey1]
+      const int lay = (jr1 - jr0 + 1) * nx;      // staged nodes per plane
+      const int elay = (ey1 - jr0 + 1) * EX;     // elements per layer
+      const int nc = (je - j0) * nx;             // output nodes per plane
+      const int gn0 = jr0 * nx, ge0 = jr0 * EX, go0 = j0 * nx;
+      T* __restrict__ S = P + 6 * lay;           // [4][elay] sums for plane k
+      T* __restrict__ TP = S + 4 * elay;         // [4][elay] top-face contributions (per thread)
+      T* __restrict__ Q = TP + 4 * elay;         // [2][nc] f2, f3 on plane k (per thread)
+      // [elay] conductivities (per thread), 8-byte aligned after Q
+      double* __restrict__ SG = reinterpret_cast<double*>(
+          smem + (((size_t)(6 * lay + 8 * elay + 2 * nc) * sizeof(T) + 7) & ~(size_t)7));
+      // prologue: planes 0 and 1, conductivities of layer 0
+      for (int q = tid; q < lay; q += BLOCK) {
+        P[q] = g0[gn0 + q];
+        P[lay + q] = g1[gn0 + q];
+        P[2 * lay + q] = g0[plane + gn0 + q];
+        P[3 * lay + q] = g1[plane + gn0 + q];
+      }
+      for (int q = tid; q < elay; q += BLOCK) {
+        SG[q] = sg[ge0 + q];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) TP[v * elay + q] = T(0);
+      }
+      for (int q = tid; q < nc; q += BLOCK) {
+        Q[q] = f2 ? g2[go0 + q] : T(0);
+        Q[nc + q] = f3 ? g3[go0 + q] : T(0);
+      }
+      __syncthreads();
+      int s0 = 0;  // ring slot of plane k
+      for (int k = 0; k < nz; ++k) {
+        const int s1 = s0 == 2 ? 0 : s0 + 1;
+        const int s2 = s1 == 2 ? 0 : s1 + 1;
+        STM_T0(t_za);
+        // ---- loads for later use ----
+        const bool pf = k + 2 < nz, ps = k + 1 < EZ, pq = k + 1 < nz;
+        T r0[CN], r1[CN];
+        if (pf) {
+          const STM_GLOBAL T* __restrict__ g0p = g0 + (size_t)(k + 2) * plane + gn0;
+          const STM_GLOBAL T* __restrict__ g1p = g1 + (size_t)(k + 2) * plane + gn0;
+#pragma unroll
+          for (int c = 0; c < CN; ++c) {
+            const int q = tid + c * BLOCK;
+            if (q < lay) {
+              r0[c] = g0p[q];
+              r1[c] = g1p[q];
+            }
+          }
+        }
+        double rs[CE];
+        if (ps) {
+          const STM_GLOBAL double* __restrict__ gsp = sg + (size_t)(k + 1) * eplane + ge0;
+#pragma unroll
+          for (int c = 0; c < CE; ++c) {
+            const int q = tid + c * BLOCK;
+            if (q < elay) rs[c] = gsp[q];
+          }
+        }
+        T r2[CB], r3[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int q = tid + c * BLOCK;
+          r2[c] = (f2 && pq && q < nc) ? g2[(size_t)(k + 1) * plane + go0 + q] : T(0);
+          r3[c] = (f3 && pq && q < nc) ? g3[(size_t)(k + 1) * plane + go0 + q] : T(0);
+        }
+        const T* __restrict__ a0 = P + (2 * s0) * lay;
+        const T* __restrict__ a1 = P + (2 * s0 + 1) * lay;
+        // ---- phase A: element layer k ----
+        if (k < EZ) {
+          const T* __restrict__ b0 = P + (2 * s1) * lay;
+          const T* __restrict__ b1 = P + (2 * s1 + 1) * lay;
+          // the layer's fibre row (uniform: scalar loads) folded with the
+          // element constants: ax = cxx (s c2 + tau s2), ay = cyy (s s2 + tau c2),
+          // az = czz (s zr + tau), axy = cxy (s - tau) cs for conductivity s
+          const double c2 = fib[kFibStride * k], s2 = fib[kFibStride * k + 1], cs = fib[kFibStride * k + 2];
+          const T kx1 = T(c2) * cxx, kx0 = T(tau * s2) * cxx;
+          const T ky1 = T(s2) * cyy, ky0 = T(tau * c2) * cyy;
+          const T kz1 = T(zr) * czz, kz0 = T(tau) * czz;
+          const T kxy = T(cs) * cxy, tauT = T(tau);
+          // every LDS read of an element is issued before its arithmetic (a
+          // scheduling barrier keeps the compiler from interleaving them with
+          // waits), so one LDS round trip per element
+#pragma unroll 1
+          for (int q = tid; q < elay; q += BLOCK) {
+            const int o = q + (int)fdiv(q, mex);  // staged node of the element's vertex (0, 0)
+            T x0[8], x1[8], tp[4];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              const int off = o + (v & 1) + ((v >> 1) & 1) * nx;
+              x0[v] = (v & 4) ? b0[off] : a0[off];
+              x1[v] = (v & 4) ? b1[off] : a1[off];
+            }
+            const double se = SG[q];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tp[v] = TP[v * elay + q];
+            __builtin_amdgcn_sched_barrier(0);
+            T kv[8], mv[8], out[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              kv[v] = kval(x0[v], x1[v]);
+              mv[v] = mval(x0[v], x1[v]);
+            }
+            const T sT = T(se);
+            elem_apply_3d<T>(kv, mv, sT * kx1 + kx0, sT * ky1 + ky0, sT * kz1 + kz0, (sT - tauT) * kxy, cm, out);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              S[v * elay + q] = tp[v] + out[v];
+              TP[v * elay + q] = out[v + 4];
+            }
+          }
+        } else {
+#pragma unroll 1
+          for (int q = tid; q < elay; q += BLOCK) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S[v * elay + q] = TP[v * elay + q];
+          }
+        }
+        STM_T1P(t_za, 6);
+        STM_T0(t_zb);
+        __syncthreads();
+        // ---- phase B: output nodes of plane k ----
+#pragma unroll 1
+        for (int q = tid; q < nc; q += BLOCK) {
+          const int r = fdiv(q, mnx);
+          const int i = q - r * nx;
+          const int j = j0 + r;
+          T cv[4];
+          bool ok[4];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const int ey = j - 1 + b;
+            const bool oky = ey >= 0 && ey < EY;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+              const int ex = i - 1 + a;
+              ok[2 * b + a] = oky && ex >= 0 && ex < EX;
+              const int el = (ey - jr0) * EX + ex;
+              const int v = (1 - a) + 2 * (1 - b);
+              cv[2 * b + a] = S[v * elay + (ok[2 * b + a] ? el : 0)];
+            }
+          }
+          const int o = (j - jr0) * nx + i;
+          const T o0 = a0[o], o1 = a1[o], o2 = Q[q], o3 = Q[nc + q];
+          __builtin_amdgcn_sched_barrier(0);
+          T y = T(0);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) y += ok[e] ? cv[e] : T(0);
+          body(k * plane + go0 + q, i, j, k, y, o0, o1, o2, o3);
+        }
+        // ---- loaded values to LDS (their latency overlapped both phases):
+        // plane k+2 into the free ring slot, the conductivities of layer k+1
+        // and f2, f3 on plane k+1 into this thread's own entries ----
+        if (pf) {
+          T* __restrict__ d0 = P + (2 * s2) * lay;
+          T* __restrict__ d1 = P + (2 * s2 + 1) * lay;
+#pragma unroll
+          for (int c = 0; c < CN; ++c) {
+            const int q = tid + c * BLOCK;
+            if (q < lay) {
+              d0[q] = r0[c];
+              d1[q] = r1[c];
+            }
+          }
+        }
+        if (ps) {
+#pragma unroll
+          for (int c = 0; c < CE; ++c) {
+            const int q = tid + c * BLOCK;
+            if (q < elay) SG[q] = rs[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const int q = tid + c * BLOCK;
+          if (pq && q < nc) {
+            Q[q] = r2[c];
+            Q[nc + q] = r3[c];
+          }
+        }
+        __syncthreads();
+        STM_T1P(t_zb, 7);
+        s0 = s1;
+      }
+    }
+    if (G > 1) team_barrier();
+  }
+
+  // ---- tiled pass (2D) --------------------------------------------------------
+  template <typename T, typename KV, typename MV, typename Body>
+  __device__ __forceinline__ void staged_tiles(int l, const T* __restrict__ f0, const T* __restrict__ f1,
+                                               const T* __restrict__ f2, const T* __restrict__ f3, KV kval, MV mval,
+                                               Body body) const {
     constexpr int NV = (DIM == 3) ? 8 : 4;
     constexpr int U = 4;                      // batched loads per thread in the staging loop
     constexpr int UA = (DIM == 3) ? 1 : 2;    // independent elements per thread in phase A
@@ -520,7 +794,7 @@ struct Team {
     }
     staged<TI>(
         l, x, w, b, di, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
-        [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { out[idx] = xo + om * (bo - y) * dio; });
+        [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { gmem(out)[idx] = xo + om * (bo - y) * dio; });
   }
 
   // Two Jacobi sweeps on grid 0 in one pass over the tiles (2D):
@@ -832,7 +1106,7 @@ struct Team {
     const TI* __restrict__ w = mgW(l);
     staged<TI>(
         l, x, w, b, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
-        [](TI a, TI ww) { return ww * a; }, [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { out[idx] = bo - y; });
+        [](TI a, TI ww) { return ww * a; }, [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { gmem(out)[idx] = bo - y; });
   }
 
   // coarse[l+1] = P^T fine[l]  (full weighting, transpose of Q1 interpolation); G == 1 only
@@ -993,7 +1267,7 @@ struct Team {
           [](TI a, TI ww) { return ww * a; },
           [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
             const TI y = ax * dio;
-            x1[idx] = y;
+            gmem(x1)[idx] = y;
             nn[0] += double(y) * double(y);
             nn[1] += double(xown) * double(xown);
           });
@@ -1218,9 +1492,9 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
               [&](int idx, int i, int j, int k, double y, double uown, double, double kd, double) {
                 const double r = -y;
                 const double w = inv_dt - react_d(uown, kr, ar);
-                V0[idx] = TI(r);
-                w0[idx] = TI(w);
-                di[idx] = TI(1.0 / (th * kd + tm.nel(0, i, j, k) * cmd * w));
+                gmem(V0)[idx] = TI(r);
+                gmem(w0)[idx] = TI(w);
+                gmem(di)[idx] = TI(1.0 / (th * kd + tm.nel(0, i, j, k) * cmd * w));
                 rr[0] += r * r;
               });
         }
@@ -1306,7 +1580,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           tm.template staged<TI>(
               0, Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
               [](TI a, TI ww) { return ww * a; },
-              [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { Vn[idx] = w; });
+              [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { gmem(Vn)[idx] = w; });
           STM_T1(t_pa, 2);
           // Classical Gram-Schmidt against V_0..V_j, done twice when the inner
           // vectors are float32 (CGS2: the second pass restores the orthogonality

@@ -181,6 +181,10 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
         return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": team_seconds must be finite and >= 0");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
+    // a 3D pass gives each thread at most five staged node columns of a tile
+    // row (one row plus two halo rows at 256 threads per workgroup)
+    if (p.dim == 3 && L.nx > 400)
+      return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": 3D rows are limited to 400 nodes");
     if ((int64_t)L.nx * L.ny * nz * std::max(L.nx, L.ny) >= (int64_t)1 << 32)
       return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": grid too large for 32-bit index arithmetic");
     if (l > 0) {
@@ -335,7 +339,30 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   // LDS tiles: maximise interior / staged nodes within the staging budget,
   // per field size and number of staged nodal fields (2 to 4)
   const size_t budget = (size_t)c->stage_bytes;
-  for (int k = 0; k < nmg; ++k) {
+  for (int k = 0; k < nmg && p.dim == 3; ++k) {
+    // 3D passes march through the planes: a ring of three planes of two nodal
+    // fields over the tile's rows plus a one-row halo, four partial sums and
+    // four top-face contributions per element of one layer, two nodal fields
+    // over the tile's rows and the layer's conductivities (float64).  The
+    // tallest tile within the budget (the kernel lowers it further to its
+    // per-thread counts).
+    const GridDev& gk = d.g[k];
+    for (int es = 0; es < 2; ++es) {
+      const size_t fb = es == 0 ? 8 : 4;
+      int by = 0;
+      for (int ry = 1; ry <= gk.ny; ++ry) {
+        const size_t sy = std::min(ry + 2, gk.ny), sey = std::min(ry + 1, gk.ey);
+        if (fb * (6 * sy * gk.nx + 8 * sey * gk.ex + 2 * (size_t)ry * gk.nx) + 8 * sey * gk.ex + 8 > budget) break;
+        by = ry;
+      }
+      if (by == 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
+      for (int nfl = 2; nfl <= 4; ++nfl) {
+        d.tile_y[k][es][nfl - 2] = by;
+        d.tile_z[k][es][nfl - 2] = 1;
+      }
+    }
+  }
+  for (int k = 0; k < nmg && p.dim == 2; ++k) {
     const GridDev& gk = d.g[k];
     for (int es = 0; es < 2; ++es) {
       const size_t fb = es == 0 ? 8 : 4;

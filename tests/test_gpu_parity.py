@@ -281,11 +281,12 @@ def test_st_solve_3d_fp64_matches_oracle(torch_dev):
 @pytest.mark.parametrize("shape,precision,G", [((9, 9, 9), "fp64", 1), ((9, 9, 9), "mixed", 3),
                                                ((17, 17, 9), "fp64", 1), ((17, 17, 9), "fp64", 3),
                                                ((17, 17, 9), "mixed", 1), ((17, 17, 9), "mixed", 3)])
-def test_rot3d_fibres_on_many_z_tiles_match_oracle(torch_dev, shape, precision, G):
-    """The fibre angle changes with every element layer (rot3d).  A 16 KiB
-    staging budget cuts the 9 node planes into tiles of one or two planes, so
-    every staged pass (2, 3 and 4 staged fields) reads its fibre rows at a
-    per-tile layer offset; teams of 3 add row bands."""
+def test_rot3d_fibres_on_many_tiles_match_oracle(torch_dev, shape, precision, G):
+    """The fibre angle changes with every element layer (rot3d), and a 3D pass
+    reads the layer's fibre row at every plane it marches through.  A 16 KiB
+    staging budget cuts the rows into several tiles (each marching through all
+    planes from its own prologue), for every staged pass (2, 3 and 4 fields);
+    teams of 3 add row bands."""
     torch, dev = torch_dev
     from paper_1911_06066_amd import Context
     wl = stinputs.workload("slab3d", levels=[shape], steps=[6], n_modes=8, kl_grid=(9, 9, 3),
