@@ -293,6 +293,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=24.0, help="seconds of oracle work (0 = skip)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the per-level smoother tuning file")
+    ap.add_argument("--st-mode", default="slab", choices=["slab", "global"],
+                    help="slab: Newton slab by slab (default); global: Newton on the whole space-time "
+                         "system with one GMRES over all slabs")
     ap.add_argument("--compare", type=int, default=1,
                     help="also time the batched path in the other precision and the single-sample float64 "
                          "path (0 = skip)")
@@ -328,6 +331,8 @@ def main():
         over["max_lanes"] = args.max_lanes
     if args.block:
         over["block_threads"] = args.block
+    if args.st_mode == "global":
+        over["st_mode"] = 1
     allocation = None
     with Context(wl, **over) as ctx:
         if wl["samples"] is None:
@@ -373,7 +378,7 @@ def main():
     kernel_s = float(np.mean(solve_ms)) * 1e-3
     achieved = float(np.mean(model_bytes)) / kernel_s / 1e9
     achieved_fused = float(np.mean(solve_bytes)) / kernel_s / 1e9
-    default_cfg = not (args.precision or args.max_lanes or args.block or args.no_tuning)
+    default_cfg = not (args.precision or args.max_lanes or args.block or args.no_tuning or args.st_mode != "slab")
     traffic = profiled_traffic(wl["name"]) if default_cfg else None
 
     line = {
@@ -400,6 +405,7 @@ def main():
             "precision": wl["precision"],
             "parallelism": "single GPU, one workgroup team per sample",
             "smoother_per_level": [list(t[:2]) for t in tuning] if tuning else "defaults",
+            "st_mode": args.st_mode,
         },
         "dof_steps_per_s": dof_steps / (ms / 1e3),
         "roofline": {

@@ -162,6 +162,14 @@ typedef struct {
   int newton_damping;         /* 0 (default) or 1: a slab's Newton step is halved (down to 1/64 of it)
                                  while the FP64 residual 2-norm it leads to exceeds the last accepted
                                  one; -1: full Newton steps */
+  int st_mode;                /* 0 (default): Newton slab by slab in time order (exact block forward
+                                 substitution of the space-time system, Sec. 3.2 eq. system_C);
+                                 1: Newton on the whole space-time system, each linear step one GMRES
+                                 over all m slabs right-preconditioned by forward substitution with
+                                 the slab preconditioner (Sec. 3.2, Sec. 3.5: the paper's monolithic,
+                                 parallel-in-time solve).  Mode 1 needs (restart + 4) m n inner
+                                 words of workspace per concurrent sample and 256 or 512 threads
+                                 per workgroup */
 } stm_problem;
 
 /* Per-sample solver statistics (host array filled by stm_st_solve). */

@@ -62,6 +62,7 @@ class StmProblem(ctypes.Structure):
         ("ic_kind", ctypes.c_int),
         ("qoi", ctypes.c_int),
         ("newton_damping", ctypes.c_int),
+        ("st_mode", ctypes.c_int),
     ]
 
 

@@ -164,6 +164,7 @@ struct Team {
   unsigned char* smem;   // dynamic LDS staging area
   double* kdiag0;        // diagonal of the stiffness matrix on grid 0 (per sample)
   TI* dinv;              // inverse diagonal of the slab operator on grid 0 (per Newton step)
+  TI* w0;                // reaction weights 1/dt - f'(u) of the slab operator on grid 0
   double* omega;         // shared: per grid, the sweep weights [kMaxMG][kMaxSweeps]
   double* red;           // shared: block reduction scratch
   // team membership
@@ -189,7 +190,9 @@ struct Team {
   }
   __device__ __forceinline__ TI* mgT(int l) const { return reinterpret_cast<TI*>(work + L->off_mgT[l]); }
   __device__ __forceinline__ TI* mgB(int l) const { return reinterpret_cast<TI*>(work + L->off_mgB[l]); }
-  __device__ __forceinline__ TI* mgW(int l) const { return reinterpret_cast<TI*>(work + L->off_mgW[l]); }
+  __device__ __forceinline__ TI* mgW(int l) const {
+    return l == 0 ? w0 : reinterpret_cast<TI*>(work + L->off_mgW[l]);
+  }
   // inverse slab diagonal, conductivities and stiffness diagonal of grid l
   __device__ __forceinline__ TI* mgI(int l) const {
     return l == 0 ? dinv : reinterpret_cast<TI*>(work + L->off_mgI[l]);
@@ -747,6 +750,95 @@ struct Team {
       }
     }
     if (G > 1) team_barrier();
+  }
+
+  // ---- per-sample operator data ----------------------------------------------
+  // On every coarse V-cycle grid (one-workgroup teams): the conductivity of an
+  // element = mean of its 2^d children, and the stiffness diagonal from it and
+  // the grid's own fibre rows (rediscretisation).  On grid 0: the stiffness
+  // diagonal at the owned nodes.  Ends with a team barrier.
+  __device__ __forceinline__ void setup_operator() const {
+    const int tid = threadIdx.x;
+    const double tau = prm.tau, zr = prm.zr;
+    for (int l = 1; l < (MG ? L->nmg : 1); ++l) {
+      const GridDev& gc = L->g[l];
+      const GridDev& gf = L->g[l - 1];
+      double* Sc = const_cast<double*>(mgS(l));
+      const double* Sf = mgS(l - 1);
+      for (int e = tid; e < gc.ne; e += BLOCK) {
+        const int E = e % gc.ex;
+        const int F = (DIM == 2) ? e / gc.ex : (e / gc.ex) % gc.ey;
+        const int Gz = (DIM == 2) ? 0 : e / (gc.ex * gc.ey);
+        double acc = 0.0;
+        const int cz = (DIM == 3) ? 2 : 1;
+        for (int c = 0; c < cz; ++c)
+          for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+              const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * Gz + c;
+              acc += Sf[(DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx)];
+            }
+        Sc[e] = acc / (4 * cz);
+      }
+      __syncthreads();
+      double* Kc = mgK(l);
+      const double* fibc = L->fib[l];
+      for (int idx = tid; idx < gc.n; idx += BLOCK) {
+        int i, j, k;
+        decode<DIM>(gc, idx, i, j, k);
+        auto z = [&](int, int, int) { return 0.0; };
+        double dd;
+        apply_at<double, DIM>(
+            gc, i, j, k, z, z,
+            [&](int ex, int ey, int ez) {
+              const int e = (DIM == 3) ? ((ez * gc.ey + ey) * gc.ex + ex) : (ey * gc.ex + ex);
+              return tensor_from<double, DIM>(Sc[e], fibc + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
+            },
+            0.0, &dd);
+        Kc[idx] = dd;
+      }
+      __syncthreads();
+    }
+    const GridDev& g0 = L->g[0];
+    const int nb = nband();
+    for (int q = tid; q < nb; q += BLOCK) {
+      const int idx = bidx(q);
+      int i, j, k;
+      decode<DIM>(g0, idx, i, j, k);
+      auto z = [&](int, int, int) { return 0.0; };
+      double dd;
+      apply_at<double, DIM>(
+          g0, i, j, k, z, z,
+          [&](int ex, int ey, int ez) {
+            const int e = (DIM == 3) ? ((ez * g0.ey + ey) * g0.ex + ex) : (ey * g0.ex + ex);
+            return tensor_from<double, DIM>(sigma[e], L->fib[0] + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
+          },
+          0.0, &dd);
+      kdiag0[idx] = dd;
+    }
+    sync();
+  }
+
+  // Reaction weights injected from grid-0 values u and the slab diagonal on
+  // every coarse V-cycle grid (one-workgroup teams; no barrier).
+  __device__ __forceinline__ void coarse_weights(const double* __restrict__ u, double inv_dt) const {
+    const GridDev& g0 = L->g[0];
+    const double kr = prm.k_react, ar = prm.a_react, th = prm.theta;
+    for (int l = 1; l < (MG ? L->nmg : 1); ++l) {
+      const GridDev& gc = L->g[l];
+      TI* wl = mgW(l);
+      TI* dl = mgI(l);
+      const double* Kc = mgK(l);
+      const double cmc = (DIM == 3) ? 8.0 * gc.hx * gc.hy * gc.hz / 216.0 : 4.0 * gc.hx * gc.hy / 36.0;
+      const int st = 1 << l;
+      for (int idx = threadIdx.x; idx < gc.n; idx += BLOCK) {
+        int I, J, K;
+        decode<DIM>(gc, idx, I, J, K);
+        const int q = (DIM == 3) ? (((K * st) * g0.ny + J * st) * g0.nx + I * st) : ((J * st) * g0.nx + I * st);
+        const double w = inv_dt - react_d(u[q], kr, ar);
+        wl[idx] = TI(w);
+        dl[idx] = TI(1.0 / (th * Kc[idx] + nel(l, I, J, K) * cmc * w));
+      }
+    }
   }
 
   // number of elements adjacent to node (i, j, k) of grid l
@@ -1350,6 +1442,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   tm.V = reinterpret_cast<TI*>(task.work + L->off_V);
   tm.kdiag0 = reinterpret_cast<double*>(task.work + L->off_kd);
   tm.dinv = reinterpret_cast<TI*>(task.work + L->off_dinv);
+  tm.w0 = reinterpret_cast<TI*>(task.work + L->off_mgW[0]);
   tm.Z = reinterpret_cast<TI*>(task.work + L->off_Z);
   const int64_t vs = (int64_t)((n0 + 63) & ~63);
   tm.vstride = vs;
@@ -1375,64 +1468,11 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
     if (task.u_guess) W = task.u_guess + (int64_t)s * m * n0;
     else if (have_prev) W = prevU;
 
-    // ---- per-sample setup of the coarse V-cycle grids (one-workgroup teams):
-    // conductivity = mean of the element's 2^d children, stiffness diagonal
-    // from it and the grid's own fibre rows (rediscretisation) ----
-    for (int l = 1; l < (MG ? L->nmg : 1); ++l) {
-      const GridDev& gc = L->g[l];
-      const GridDev& gf = L->g[l - 1];
-      double* Sc = const_cast<double*>(tm.mgS(l));
-      const double* Sf = tm.mgS(l - 1);
-      for (int e = tid; e < gc.ne; e += BLOCK) {
-        const int E = e % gc.ex;
-        const int F = (DIM == 2) ? e / gc.ex : (e / gc.ex) % gc.ey;
-        const int Gz = (DIM == 2) ? 0 : e / (gc.ex * gc.ey);
-        double acc = 0.0;
-        const int cz = (DIM == 3) ? 2 : 1;
-        for (int c = 0; c < cz; ++c)
-          for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a) {
-              const int fx = 2 * E + a, fy = 2 * F + b, fz = 2 * Gz + c;
-              acc += Sf[(DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx)];
-            }
-        Sc[e] = acc / (4 * cz);
-      }
-      __syncthreads();
-      double* Kc = tm.mgK(l);
-      const double* fibc = L->fib[l];
-      for (int idx = tid; idx < gc.n; idx += BLOCK) {
-        int i, j, k;
-        decode<DIM>(gc, idx, i, j, k);
-        auto z = [&](int, int, int) { return 0.0; };
-        double dd;
-        apply_at<double, DIM>(
-            gc, i, j, k, z, z,
-            [&](int ex, int ey, int ez) {
-              const int e = (DIM == 3) ? ((ez * gc.ey + ey) * gc.ex + ex) : (ey * gc.ex + ex);
-              return tensor_from<double, DIM>(Sc[e], fibc + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
-            },
-            0.0, &dd);
-        Kc[idx] = dd;
-      }
-      __syncthreads();
-    }
-    // diagonal of the stiffness matrix on grid 0 (sigma is fixed for the sample),
+    tm.setup_operator();
     // initial state, activation markers, warm-start history
     tm.bytes = uni(tm.bytes + ((24.0 + sizeof(TI) + 24.0) * n0));
     for (int q = tid; q < nb; q += BLOCK) {
       const int idx = tm.bidx(q);
-      int i, j, k;
-      decode<DIM>(g0, idx, i, j, k);
-      auto z = [&](int, int, int) { return 0.0; };
-      double dd;
-      apply_at<double, DIM>(
-          g0, i, j, k, z, z,
-          [&](int ex, int ey, int ez) {
-            const int e = (DIM == 3) ? ((ez * g0.ey + ey) * g0.ex + ex) : (ey * g0.ex + ex);
-            return tensor_from<double, DIM>(tm.sigma[e], L->fib[0] + kFibStride * ((DIM == 3) ? ez : ey), tau, zr);
-          },
-          0.0, &dd);
-      tm.kdiag0[idx] = dd;
       const double v = L->u0[idx];
       uprev[idx] = v;
       wk1[idx] = v;
@@ -1498,23 +1538,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 rr[0] += r * r;
               });
         }
-        for (int l = 1; l < (MG ? L->nmg : 1); ++l) {  // G == 1 here
-          // reaction weights injected from grid 0, the coarse slab diagonal
-          const GridDev& gc = L->g[l];
-          TI* wl = tm.mgW(l);
-          TI* dl = tm.mgI(l);
-          const double* Kc = tm.mgK(l);
-          const double cmc = (DIM == 3) ? 8.0 * gc.hx * gc.hy * gc.hz / 216.0 : 4.0 * gc.hx * gc.hy / 36.0;
-          const int st = 1 << l;
-          for (int idx = tid; idx < gc.n; idx += BLOCK) {
-            int I, J, K;
-            decode<DIM>(gc, idx, I, J, K);
-            const int q = (DIM == 3) ? (((K * st) * g0.ny + J * st) * g0.nx + I * st) : ((J * st) * g0.nx + I * st);
-            const double w = inv_dt - react_d(u[q], kr, ar);
-            wl[idx] = TI(w);
-            dl[idx] = TI(1.0 / (th * Kc[idx] + tm.nel(l, I, J, K) * cmc * w));
-          }
-        }
+        tm.coarse_weights(u, inv_dt);
         tm.template tsum<1>(rr);  // its barriers also publish the writes above
         STM_T1(t_res, 0);
         model_bytes = uni(model_bytes + 32.0 * n0);
@@ -1846,10 +1870,429 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Global space-time solve (Sec. 3.2 eq. system_C, Sec. 3.5): Newton on the
+// whole space-time system at once.  Each linear step J delta = -R is one GMRES
+// over all m slabs, right-preconditioned by forward substitution in time in
+// which every diagonal block is replaced by the slab preconditioner (one
+// V-cycle, or the Chebyshev-weighted sweeps):
+//   z_0 = P_0^-1 r_0,  z_k = P_k^-1 (r_k - B z_{k-1}),  B = -M/dt + (1 - theta) K.
+// The residual and the product J x = (A_k x_k + B x_{k-1})_k treat every slab
+// on its own (the parallel-in-time part of the method); the preconditioner
+// sweeps the slabs in order.  The step is added in float64 and halved while
+// the residual 2-norm grows, as in the slab solve; the first iterate is the
+// lane's previous solution or the caller's guess, else the initial state at
+// every time level.  Teams, tasks and statistics as in st_team_kernel
+// (newton_max_per_slab is the number of global Newton steps).
+// ---------------------------------------------------------------------------
+template <typename TI, int DIM, int BLOCK, bool MG>
+__global__ __launch_bounds__(BLOCK) void st_global_kernel(const LevelDev* __restrict__ levels,
+                                                          const TeamTask* __restrict__ tasks, SolverParams prm) {
+  constexpr int NW = BLOCK / kWave;
+  extern __shared__ __align__(16) unsigned char smem_dyn[];
+  __shared__ double red[NW * 9];
+  __shared__ double H[(kMaxRestart + 1) * kMaxRestart];
+  __shared__ double cs_[kMaxRestart], sn_[kMaxRestart], gv[kMaxRestart + 1], sc[kMaxRestart + 1];
+  __shared__ double yv[kMaxRestart], coef[kMaxRestart + 1];
+  __shared__ double omega_tab[kMaxMG * kMaxSweeps];
+  __shared__ double sh_resid;
+#ifdef STM_PHASE_TIMERS
+  __shared__ long long ph_acc[8];
+  if (threadIdx.x < 8) ph_acc[threadIdx.x] = 0;
+  __syncthreads();
+#endif
+
+  const TeamTask task = tasks[blockIdx.x];
+  const LevelDev* L = levels + task.level;
+  const int tid = threadIdx.x;
+
+  Team<TI, DIM, BLOCK, MG> tm;
+  tm.L = L;
+  tm.prm = prm;
+  tm.work = task.work;
+  tm.smem = smem_dyn;
+  tm.omega = omega_tab;
+  tm.red = red;
+  tm.bytes = 0.0;
+  tm.rank = task.rank;
+  tm.G = task.G;
+  tm.bar = task.bar;
+  tm.part = task.part;
+  tm.fault = task.fault;
+  tm.gen = 0;
+  tm.rslot = 0;
+  tm.broken = false;
+#ifdef STM_PHASE_TIMERS
+  tm.ph = ph_acc;
+#endif
+  const GridDev g0 = L->g[0];
+  tm.jb0 = (int)((long long)task.rank * g0.ny / task.G);
+  tm.jb1 = (int)((long long)(task.rank + 1) * g0.ny / task.G);
+  const int n0 = g0.n;
+  const int nb = tm.nband();
+  double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
+  tm.V = reinterpret_cast<TI*>(task.work + L->off_V);  // slab-sized scratch of the power iteration
+  tm.Z = reinterpret_cast<TI*>(task.work + L->off_Z);
+  tm.kdiag0 = reinterpret_cast<double*>(task.work + L->off_kd);
+  tm.dinv = reinterpret_cast<TI*>(task.work + L->off_dinv);
+  tm.w0 = reinterpret_cast<TI*>(task.work + L->off_mgW[0]);
+  const int64_t vs = (int64_t)((n0 + 63) & ~63);
+  tm.vstride = vs;
+  const int m = L->m;
+  const int64_t gs = (int64_t)m * vs;  // stride of space-time vectors
+  TI* __restrict__ gV = reinterpret_cast<TI*>(task.work + L->off_gV);
+  TI* __restrict__ gW = reinterpret_cast<TI*>(task.work + L->off_gW);
+  TI* __restrict__ gD = reinterpret_cast<TI*>(task.work + L->off_gD);
+  TI* __restrict__ gZ = reinterpret_cast<TI*>(task.work + L->off_gZ);
+  TI* __restrict__ gT = reinterpret_cast<TI*>(task.work + L->off_gT);
+  double* ubuf = reinterpret_cast<double*>(task.work + L->off_U);
+
+  const double dt = uni(L->dt), inv_dt = uni(1.0 / L->dt);
+  const double kr = uni(prm.k_react), ar = uni(prm.a_react), thr = uni(prm.threshold);
+  const double th = uni(prm.theta);
+  const double cmd = (DIM == 3) ? 8.0 * g0.hx * g0.hy * g0.hz / 216.0 : 4.0 * g0.hx * g0.hy / 36.0;
+  const int restart = prm.restart;
+
+  bool have_prev = false;
+  const double* prevU = nullptr;
+
+  for (int it_s = 0; it_s < task.count; ++it_s) {
+    const int s = task.order ? task.order[task.first + it_s * task.stride] : task.first + it_s * task.stride;
+    const long long t_start = wall_clock64();
+    tm.bytes = 0.0;
+    tm.sigma = task.sigma + (int64_t)s * g0.ne;
+    double* __restrict__ U = task.u_out ? task.u_out + (int64_t)s * m * n0 : ubuf;
+    const double* W = nullptr;
+    if (task.u_guess) W = task.u_guess + (int64_t)s * m * n0;
+    else if (have_prev) W = prevU;
+
+    tm.setup_operator();
+    // first iterate: the guess, else the initial state at every time level
+    tm.bytes = uni(tm.bytes + 16.0 * (double)m * n0);
+    for (int k = 0; k < m; ++k)
+      for (int q = tid; q < nb; q += BLOCK) {
+        const int idx = tm.bidx(q);
+        U[(int64_t)k * n0 + idx] = W ? W[(int64_t)k * n0 + idx] : L->u0[idx];
+      }
+    tm.sync();
+
+    // z = P^-1 r over the space-time vectors r, z: forward substitution in time
+    auto precond = [&](const TI* __restrict__ r, TI* __restrict__ z) {
+      for (int k = 0; k < m; ++k) {
+        tm.w0 = gW + k * vs;
+        tm.dinv = gD + k * vs;
+        if (MG) tm.coarse_weights(U + (int64_t)k * n0, inv_dt);
+        const TI* b = r + k * vs;
+        if (k > 0) {
+          tm.template staged<TI>(
+              0, z + (k - 1) * vs, r + k * vs, (const TI*)nullptr, (const TI*)nullptr,
+              [c1 = TI(1.0 - th)](TI a, TI) { return c1 * a; }, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
+              [&](int idx, int, int, int, TI y, TI, TI ro, TI, TI) { gmem(gT)[idx] = ro - y; });
+          b = gT;
+        }
+        tm.vcycle(b, z + k * vs);
+      }
+    };
+    // y = J x: slab products and the coupling to the previous slab
+    auto spmv = [&](const TI* __restrict__ x, TI* __restrict__ y) {
+      for (int k = 0; k < m; ++k) {
+        TI* yk = y + k * vs;
+        tm.template staged<TI>(
+            0, x + k * vs, gW + k * vs, (const TI*)nullptr, (const TI*)nullptr,
+            [c1 = TI(th)](TI a, TI) { return c1 * a; }, [](TI a, TI ww) { return ww * a; },
+            [&](int idx, int, int, int, TI v, TI, TI, TI, TI) { gmem(yk)[idx] = v; });
+        if (k > 0)
+          // in place: f1 = y_k enters only the body (its own node), never the element terms
+          tm.template staged<TI>(
+              0, x + (k - 1) * vs, yk, (const TI*)nullptr, (const TI*)nullptr,
+              [c1 = TI(1.0 - th)](TI a, TI) { return c1 * a; }, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
+              [&](int idx, int, int, int, TI v, TI, TI yo, TI, TI) { gmem(yk)[idx] = yo + v; });
+      }
+    };
+
+    long long krylov_total = 0, damped = 0;
+    int status = 0;
+    // per-step word model: 4 float64 words per node and slab per residual; per
+    // Krylov iteration j, per node and slab: 4 (slab product) + 4 (coupling) +
+    // 4 (coupling in the substitution) + the slab preconditioner's words +
+    // 2j + 3 (Arnoldi step) inner words
+    double model_bytes = 0.0;
+    const double krylov_words = 15.0 + L->pc_words;
+    const double nm = (double)m * n0;
+    bool weights_ready = (prm.smoother == 0);
+    double dprev = 0.0, eta = fmax(prm.gmres_rtol, 1e-5), dmax = 0.0;
+    double beta_acc = 0.0, tstep = 1.0;
+    bool conv = false;
+    int it = 0;
+    for (; it < prm.newton_max; ++it) {
+      // ---- residual of every slab (float64) -> V_0 = -R, weights and inverse diagonals ----
+      double rr[1] = {0.0};
+      tm.bytes = uni(tm.bytes + (24.0 * nm + 8.0 * g0.ne * m + 3.0 * sizeof(TI) * nm));
+      for (int k = 0; k < m; ++k) {
+        const double* uk = U + (int64_t)k * n0;
+        const double* up = k ? U + (int64_t)(k - 1) * n0 : L->u0;
+        TI* Vk = gV + k * vs;
+        TI* wk = gW + k * vs;
+        TI* dk = gD + k * vs;
+        tm.template staged<double>(
+            0, uk, up, tm.kdiag0, (const double*)nullptr,
+            [th](double a, double b) { return th * a + (1.0 - th) * b; },
+            [&](double a, double b) { return (a - b) * inv_dt - react(a, kr, ar); },
+            [&](int idx, int i, int j, int kk, double y, double uown, double, double kd, double) {
+              const double r = -y;
+              const double w = inv_dt - react_d(uown, kr, ar);
+              gmem(Vk)[idx] = TI(r);
+              gmem(wk)[idx] = TI(w);
+              gmem(dk)[idx] = TI(1.0 / (th * kd + tm.nel(0, i, j, kk) * cmd * w));
+              rr[0] += r * r;
+            });
+      }
+      tm.template tsum<1>(rr);
+      model_bytes = uni(model_bytes + 32.0 * nm);
+      const double beta = uni(sqrt(rr[0]));
+      if (!isfinite(beta) && !(prm.damping && it > 0 && tstep > kMinStep)) {
+        status = -5;
+        break;
+      }
+      if (beta == 0.0) {
+        conv = true;
+        dmax = 0.0;
+        break;
+      }
+      // the last step made the residual grow: take half of it back
+      if (prm.damping && it > 0 && !(beta <= beta_acc) && tstep > kMinStep) {
+        tstep = uni(0.5 * tstep);
+        for (int k = 0; k < m; ++k)
+          for (int q = tid; q < nb; q += BLOCK) {
+            const int idx = tm.bidx(q);
+            U[(int64_t)k * n0 + idx] -= tstep * double(gZ[k * vs + idx]);
+          }
+        tm.bytes = uni(tm.bytes + (16.0 + sizeof(TI)) * nm);
+        dmax = uni(0.5 * dmax);
+        ++damped;
+        tm.sync();
+        continue;
+      }
+      beta_acc = beta;
+      tstep = 1.0;
+      // ---- smoother weights: once per sample, from the first slab operator ----
+      if (!weights_ready) {
+        tm.w0 = gW;
+        tm.dinv = gD;
+        if (MG) tm.coarse_weights(U, inv_dt);
+        for (int l = 0; l < (MG ? L->nmg : 1); ++l) {
+          TI* x0 = (l == 0) ? tm.V + vs : tm.mgX(l);
+          TI* x1 = (l == 0) ? tm.V + 2 * vs : tm.mgT(l);
+          const double lmax = 1.05 * tm.power_lmax(l, x0, x1);
+          const int K = (l == L->nmg - 1) ? L->sweeps : prm.smooth_steps;
+          if (tid == 0) chebyshev_weights(lmax / L->cheb_ratio, lmax, K, omega_tab + l * kMaxSweeps);
+        }
+        __syncthreads();
+        weights_ready = true;
+      }
+
+      // ---- GMRES(restart) over the space-time vectors ----
+      if (tid == 0) {
+        sc[0] = 1.0 / beta;
+        gv[0] = beta;
+      }
+      __syncthreads();
+      const double tol_abs = uni(eta * beta);
+      int jdim = 0;
+      for (int j = 0; j < restart; ++j) {
+        const TI* Vj = gV + j * gs;
+        TI* Vn = gV + (j + 1) * gs;
+        model_bytes = uni(model_bytes + double(sizeof(TI)) * nm * (krylov_words + 2.0 * j));
+        precond(Vj, gZ);
+        spmv(gZ, Vn);
+        // Classical Gram-Schmidt against V_0..V_j, twice for float32 (CGS2)
+        double nn[1] = {0.0};
+        constexpr int kPasses = sizeof(TI) == 4 ? 2 : 1;
+#pragma unroll 1
+        for (int pass = 0; pass < kPasses; ++pass) {
+          for (int k0 = 0; k0 <= j; k0 += 8) {
+            const int nk = min(j + 1 - k0, 8);
+            tm.bytes = uni(tm.bytes + ((1.0 + nk) * sizeof(TI) * nm));
+            double d[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) d[q] = 0.0;
+            for (int k = 0; k < m; ++k)
+              for (int q = tid; q < nb; q += BLOCK) {
+                const int64_t idx = k * vs + tm.bidx(q);
+                const double wd = double(Vn[idx]);
+#pragma unroll
+                for (int p = 0; p < 8; ++p)
+                  if (p < nk) d[p] += double(gV[(k0 + p) * gs + idx]) * wd;
+              }
+            tm.template tsum<9>(d);
+            if (tid == 0) {
+#pragma unroll
+              for (int q = 0; q < 8; ++q)
+                if (q < nk) coef[k0 + q] = d[q];
+            }
+          }
+          // projections onto the normalised basis enter H; V_q is stored with
+          // norm 1/sc[q], so w loses (sc[q]^2 <V_q, w>) V_q
+          if (tid == 0)
+            for (int q = 0; q <= j; ++q) {
+              const double hq = sc[q] * sc[j] * coef[q];
+              H[q * kMaxRestart + j] = (pass ? H[q * kMaxRestart + j] : 0.0) + hq;
+              coef[q] = sc[q] * sc[q] * coef[q];
+            }
+          __syncthreads();
+          nn[0] = 0.0;
+          tm.bytes = uni(tm.bytes + ((j + 3.0) * sizeof(TI) * nm));
+          for (int k = 0; k < m; ++k)
+            for (int q = tid; q < nb; q += BLOCK) {
+              const int64_t idx = k * vs + tm.bidx(q);
+              double w = double(Vn[idx]);
+              for (int p = 0; p <= j; ++p) w -= coef[p] * double(gV[p * gs + idx]);
+              const TI wt = TI(w);
+              Vn[idx] = wt;
+              nn[0] += double(wt) * double(wt);
+            }
+          tm.template tsum<1>(nn);  // its barriers also publish V_{j+1}
+        }
+        const double hn = uni(sqrt(nn[0]));
+        if (tid == 0) {
+          const double hj1 = sc[j] * hn;
+          sc[j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+          for (int q = 0; q < j; ++q) {  // previous rotations on column j
+            const double a = H[q * kMaxRestart + j], b = H[(q + 1) * kMaxRestart + j];
+            H[q * kMaxRestart + j] = cs_[q] * a + sn_[q] * b;
+            H[(q + 1) * kMaxRestart + j] = -sn_[q] * a + cs_[q] * b;
+          }
+          const double a = H[j * kMaxRestart + j];
+          const double r = sqrt(a * a + hj1 * hj1);
+          const double c = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? hj1 / r : 0.0;
+          cs_[j] = c;
+          sn_[j] = sn;
+          H[j * kMaxRestart + j] = r;
+          H[(j + 1) * kMaxRestart + j] = 0.0;
+          gv[j + 1] = -sn * gv[j];
+          gv[j] = c * gv[j];
+          sh_resid = fabs(gv[j + 1]);
+        }
+        __syncthreads();
+        jdim = j + 1;
+        const double resid = uni(sh_resid);
+        if (!(resid > tol_abs) || !(hn > 0.0)) break;
+      }
+      krylov_total += jdim;
+      if (tid == 0) {
+        for (int q = jdim - 1; q >= 0; --q) {
+          double acc = gv[q];
+          for (int p = q + 1; p < jdim; ++p) acc -= H[q * kMaxRestart + p] * yv[p];
+          yv[q] = acc / H[q * kMaxRestart + q];
+        }
+        for (int q = 0; q < jdim; ++q) coef[q] = yv[q] * sc[q];
+      }
+      __syncthreads();
+      // ---- delta = P^-1 (sum_q y_q v_q); U += delta (float64), max-norm ----
+      TI* t = gV + jdim * gs;  // the last basis vector is no longer needed
+      tm.bytes = uni(tm.bytes + (double(jdim) + 1.0) * sizeof(TI) * nm);
+      for (int k = 0; k < m; ++k)
+        for (int q = tid; q < nb; q += BLOCK) {
+          const int64_t idx = k * vs + tm.bidx(q);
+          double acc = 0.0;
+          for (int p = 0; p < jdim; ++p) acc += coef[p] * double(gV[p * gs + idx]);
+          t[idx] = TI(acc);
+        }
+      tm.sync();
+      precond(t, gZ);
+      double dm = 0.0;
+      tm.bytes = uni(tm.bytes + (16.0 + sizeof(TI)) * nm);
+      for (int k = 0; k < m; ++k)
+        for (int q = tid; q < nb; q += BLOCK) {
+          const int idx = tm.bidx(q);
+          const double dl = double(gZ[k * vs + idx]);
+          U[(int64_t)k * n0 + idx] += dl;
+          dm = fmax(dm, fabs(dl));
+        }
+      dmax = uni(tm.tmax(dm));  // its barrier also publishes U to the other members
+      const double ach = sh_resid / beta;
+      if (!isfinite(dmax)) {
+        status = -5;
+        break;
+      }
+      if (dmax <= prm.newton_tol) {
+        conv = true;
+        ++it;
+        break;
+      }
+      if (it >= 1) {
+        const double ratio = dmax / dprev;
+        const double pred = dmax * fmax(ratio * ratio, 10.0 * ach);
+        if (ratio < 0.5 && pred <= 0.1 * prm.newton_tol) {
+          conv = true;
+          ++it;
+          break;
+        }
+      }
+      dprev = uni(dmax);
+      eta = uni(fmax(prm.gmres_rtol, fmin(1e-4, 0.01 * dmax)));
+    }
+    if (!conv && status == 0) status = -4;
+
+    // ---- activation map: first up-crossing in time at every owned node ----
+    double cen[1] = {0.0};
+    tm.bytes = uni(tm.bytes + 8.0 * nm + 16.0 * n0);
+    for (int q = tid; q < nb; q += BLOCK) {
+      const int idx = tm.bidx(q);
+      double up = L->u0[idx];
+      double t = (up >= thr) ? 0.0 : -1.0;
+      for (int k = 0; k < m; ++k) {
+        const double un = U[(int64_t)k * n0 + idx];
+        if (t < 0.0 && un >= thr) t = k * dt + dt * (thr - up) / (un - up);
+        up = un;
+      }
+      if (t < 0.0) {
+        t = L->T;
+        cen[0] += 1.0;
+      }
+      tact[idx] = t;
+      if (task.t_act) task.t_act[(int64_t)s * n0 + idx] = t;
+    }
+    tm.template tsum<1>(cen);
+    if (tid == 0 && task.stats && task.rank == 0) {
+      SampleStatsDev st;
+      st.status = tm.broken ? -3 : status;
+      st.newton_max_per_slab = it;
+      st.newton_iters = it;
+      st.krylov_iters = krylov_total;
+      st.final_step = dmax;
+      st.ticks = wall_clock64() - t_start;
+      st.censored = (int)cen[0];
+      st.damped = (int)damped;
+      st.alg_bytes = tm.bytes;
+      st.model_bytes = model_bytes;
+      for (int q = 0; q < 8; ++q) st.phase_ticks[q] = 0;
+#ifdef STM_PHASE_TIMERS
+      for (int q = 0; q < 8; ++q) st.phase_ticks[q] = ph_acc[q];
+#endif
+      task.stats[s] = st;
+    }
+#ifdef STM_PHASE_TIMERS
+    __syncthreads();
+    if (threadIdx.x < 8) ph_acc[threadIdx.x] = 0;
+#endif
+    prevU = U;
+    have_prev = (status == 0);
+    tm.sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launcher
 // ---------------------------------------------------------------------------
 template <typename TI, int DIM, bool MG>
-static const void* kernel_for_block(int block) {
+static const void* kernel_for_block(int block, bool global) {
+  if (global) {
+    switch (block) {
+      case 256: return (const void*)st_global_kernel<TI, DIM, 256, MG>;
+      case 512: return (const void*)st_global_kernel<TI, DIM, 512, MG>;
+      default: return nullptr;
+    }
+  }
   switch (block) {
     case 256: return (const void*)st_team_kernel<TI, DIM, 256, MG>;
     case 512: return (const void*)st_team_kernel<TI, DIM, 512, MG>;
@@ -1862,20 +2305,21 @@ static const void* kernel_for_block(int block) {
 // whose V-cycle has coarse grids; the others take the single-grid variant,
 // which compiles none of the coarse-grid code.
 template <int DIM>
-static const void* kernel_for_dim(bool fp32, bool mg, int block) {
-  if (mg) return fp32 ? kernel_for_block<float, DIM, true>(block) : kernel_for_block<double, DIM, true>(block);
-  return fp32 ? kernel_for_block<float, DIM, false>(block) : kernel_for_block<double, DIM, false>(block);
+static const void* kernel_for_dim(bool fp32, bool mg, int block, bool global) {
+  if (mg)
+    return fp32 ? kernel_for_block<float, DIM, true>(block, global) : kernel_for_block<double, DIM, true>(block, global);
+  return fp32 ? kernel_for_block<float, DIM, false>(block, global) : kernel_for_block<double, DIM, false>(block, global);
 }
 
-static const void* solver_kernel(int dim, bool fp32, bool mg, int block) {
-  return dim == 2 ? kernel_for_dim<2>(fp32, mg, block) : kernel_for_dim<3>(fp32, mg, block);
+static const void* solver_kernel(int dim, bool fp32, bool mg, int block, bool global) {
+  return dim == 2 ? kernel_for_dim<2>(fp32, mg, block, global) : kernel_for_dim<3>(fp32, mg, block, global);
 }
 
 hipError_t launch_team_solver(int dim, bool inner_fp32, bool mg, const LevelDev* levels, const TeamTask* tasks,
                               int n_blocks, SolverParams prm, int block, size_t lds_bytes, bool cooperative,
                               hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  const void* f = solver_kernel(dim, inner_fp32, mg, block);
+  const void* f = solver_kernel(dim, inner_fp32, mg, block, prm.global_st != 0);
   if (!f) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
@@ -1885,9 +2329,9 @@ hipError_t launch_team_solver(int dim, bool inner_fp32, bool mg, const LevelDev*
 }
 
 // Co-resident workgroups per CU for a launch configuration (0 on error).
-int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t lds_bytes) {
+int team_solver_occupancy(int dim, bool inner_fp32, bool mg, bool global, int block, size_t lds_bytes) {
   int nb = 0;
-  const void* f = solver_kernel(dim, inner_fp32, mg, block);
+  const void* f = solver_kernel(dim, inner_fp32, mg, block, global);
   if (!f) return 0;
   if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds_bytes) != hipSuccess) return 0;

@@ -161,6 +161,9 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
   if (p.ic_kind != STM_IC_BALL && p.ic_kind != STM_IC_GAUSS) return fail(c, STM_E_INVALID, "ic_kind must be 0 or 1");
   if (p.qoi != STM_QOI_ACTIVATION && p.qoi != STM_QOI_SPACETIME) return fail(c, STM_E_INVALID, "qoi must be 0 or 1");
   if (p.newton_damping < -1 || p.newton_damping > 1) return fail(c, STM_E_INVALID, "newton_damping must be -1, 0 or 1");
+  if (p.st_mode < 0 || p.st_mode > 1) return fail(c, STM_E_INVALID, "st_mode must be 0 or 1");
+  if (p.st_mode == 1 && p.block_threads == 1024)
+    return fail(c, STM_E_INVALID, "st_mode 1 runs with 256 or 512 threads per workgroup");
   if (!(p.ic_radius >= 0)) return fail(c, STM_E_INVALID, "ic_radius must be >= 0");
   if (p.ic_kind == STM_IC_GAUSS && !(p.ic_radius > 0))
     return fail(c, STM_E_INVALID, "the Gaussian initial state needs ic_radius > 0");
@@ -333,6 +336,16 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
       w += frac * 5.0 * (k + 1 < nmg ? 2 * nu + 1 : d.sweeps);
     }
     d.pc_words = w;
+  }
+  if (p.st_mode == 1) {
+    // global space-time mode: Krylov basis, per-slab weights and inverse
+    // diagonals, preconditioned vector over all m slabs, one slab temporary
+    const size_t gsz = ti * vs * (size_t)lv.m;
+    d.off_gV = take(gsz * (R + 1));
+    d.off_gW = take(gsz);
+    d.off_gD = take(gsz);
+    d.off_gZ = take(gsz);
+    d.off_gT = take(ti * vs);
   }
   out.team_bytes = (int64_t)off;
   d.off_U = off;
@@ -562,7 +575,8 @@ int max_team(const stm_ctx* c, int level) {
 
 // Workgroups that can be resident at once for the solver configuration.
 int block_capacity(stm_ctx* c, int block) {
-  const int occ = team_solver_occupancy(c->p.dim, c->inner_fp32, c->any_mg, block, (size_t)c->stage_bytes);
+  const int occ = team_solver_occupancy(c->p.dim, c->inner_fp32, c->any_mg, c->p.st_mode == 1, block,
+                                        (size_t)c->stage_bytes);
   return std::max(1, occ) * c->n_cu;
 }
 
@@ -649,6 +663,7 @@ stm_status stm_create(const stm_problem* p, void* hip_stream, stm_ctx** out) {
   s.power_iters = 40;
   s.theta = c->p.theta;
   s.damping = c->p.newton_damping >= 0 ? 1 : 0;
+  s.global_st = c->p.st_mode;
   *out = c;
   return STM_OK;
 }

@@ -59,6 +59,12 @@ struct LevelDev {
   int64_t off_mgS[kMaxMG];                              // float64 [ne_l] conductivity: mean of children (l >= 1)
   int64_t off_mgK[kMaxMG];                              // float64 [n_l] stiffness diagonal (l >= 1)
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
+  // global space-time mode only (0 otherwise): inner space-time vectors of
+  // m slabs of stride vs = n0 rounded up to 64
+  int64_t off_gV;                                       // [restart+1][m][vs] Krylov basis
+  int64_t off_gW, off_gD;                               // [m][vs] reaction weights, inverse slab diagonals
+  int64_t off_gZ;                                       // [m][vs] preconditioned vector / Newton step
+  int64_t off_gT;                                       // [vs] forward-substitution right-hand side
   int64_t team_bytes;
   // LDS tiles of the stencil passes on every grid: node rows (y) and planes
   // (z) per tile, [grid][8-byte (0) or 4-byte (1) fields][2, 3 or 4 staged
@@ -87,6 +93,7 @@ struct SolverParams {
   int power_iters;      // power iterations estimating lmax(D^-1 A) per sample and grid
   double theta;         // weight of the new time level in the diffusion term (1: BE, 1/2: CN)
   int damping;          // 1: halve a Newton step while the residual grows; 0: full steps
+  int global_st;        // 1: Newton on the whole space-time system with a global GMRES (st_global_kernel)
 };
 
 constexpr int kMaxSweeps = 32;

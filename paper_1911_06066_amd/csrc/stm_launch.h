@@ -12,11 +12,13 @@ namespace stm {
 // (staging tiles); cooperative: launch with guaranteed co-residency (needed
 // when any team has G > 1).
 // mg: some level of the launch has a multigrid hierarchy (nmg > 1).
+// prm.global_st selects the global space-time kernel (256 or 512 threads).
 hipError_t launch_team_solver(int dim, bool inner_fp32, bool mg, const LevelDev* levels, const TeamTask* tasks,
                               int n_blocks, SolverParams prm, int block, size_t lds_bytes, bool cooperative,
                               hipStream_t st);
-// Co-resident solver workgroups per CU for a configuration (0 on error).
-int team_solver_occupancy(int dim, bool inner_fp32, bool mg, int block, size_t lds_bytes);
+// Co-resident solver workgroups per CU for a configuration (0 on error);
+// global: the global space-time kernel (SolverParams::global_st).
+int team_solver_occupancy(int dim, bool inner_fp32, bool mg, bool global, int block, size_t lds_bytes);
 
 // sigma[s][e] = sigma_f0 * exp(sum_k modes[e][k] xi[s][k]) on the matrix cores.
 // split_fp16: operands split into fp16 hi/lo pairs, fp32 accumulation; else float64 MFMA.

@@ -105,6 +105,17 @@ def test_multigrid_depth_out_of_range_rejected(mg_levels):
     assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
 
 
+@pytest.mark.parametrize("over", [dict(st_mode=2), dict(st_mode=-1), dict(st_mode=1, block_threads=1024)])
+def test_space_time_mode_out_of_range_rejected(over):
+    """st_mode is 0 (slab by slab) or 1 (global space-time GMRES, 256 or 512
+    threads per workgroup)."""
+    L, lib = _lib()
+    from paper_1911_06066_amd import problem_from_workload
+    p = problem_from_workload(stinputs.workload("small_mc_2d"), **over)
+    h = ctypes.c_void_p()
+    assert lib.stm_create(ctypes.byref(p), None, ctypes.byref(h)) == -1 and not h.value
+
+
 def test_non_nested_levels_rejected():
     L, lib = _lib()
     from paper_1911_06066_amd import problem_from_workload
