@@ -170,6 +170,7 @@ struct Team {
   // team membership
   int rank, G;
   int jb0, jb1;          // owned node rows of grid 0
+  int kb0, kb1;          // owned node planes of grid 0 (3D; 0, 1 in 2D)
   unsigned* bar;
   double* part;
   int* fault;
@@ -271,9 +272,20 @@ struct Team {
   }
 
   // ---- owned nodes of grid 0 ----------------------------------------------
+  // Rows per tile of a z-marching pass on grid l with fields of fbytes bytes:
+  // the LDS budget (set on the host) and the per-thread element, staged-node
+  // and output-node counts.
+  static constexpr int kCE = 4, kCN = 5, kCB = 4;
+  __device__ __forceinline__ int zrows_max(int l, int fbytes) const {
+    const GridDev& g = L->g[l];
+    return max(1, min((int)L->tile_y[l][fbytes == 8 ? 0 : 1][0],
+                      min(kCE * BLOCK / g.ex - 1, min(kCN * BLOCK / g.nx - 2, kCB * BLOCK / g.nx))));
+  }
+  // A member owns node rows [jb0, jb1) of planes [kb0, kb1) (3D), q-th in
+  // plane-major order.
   __device__ __forceinline__ int nband() const {
     const GridDev& g = L->g[0];
-    return (jb1 - jb0) * g.nx * ((DIM == 3) ? g.nz : 1);
+    return (jb1 - jb0) * g.nx * ((DIM == 3) ? (kb1 - kb0) : 1);
   }
   __device__ __forceinline__ int bidx(int q) const {
     const GridDev& g = L->g[0];
@@ -283,8 +295,37 @@ struct Team {
       if (G == 1) return q;
       const int w = (jb1 - jb0) * g.nx;
       const int kk = q / w;
-      return (kk * g.ny + jb0) * g.nx + (q - kk * w);
+      return ((kb0 + kk) * g.ny + jb0) * g.nx + (q - kk * w);
     }
+  }
+  // The member's box of grid 0: in 3D the G members are split into Gz
+  // groups of planes and each group into G / Gz bands of rows (a z-step of a
+  // pass then carries more nodes than with bands of rows alone).
+  __device__ __forceinline__ void set_box() {
+    const GridDev& g = L->g[0];
+    int Gz = 1;
+    if constexpr (DIM == 3) {
+      // Gz minimises the z-steps of a member's pass: tiles x (planes + the
+      // step on the layer below + about two steps of prologue), every member
+      // keeping at least 4 planes
+      const int Rmax = zrows_max(0, sizeof(TI));
+      int best = -1;
+      for (int d = 1; d <= G; ++d) {
+        if (G % d != 0 || g.nz < 4 * d) continue;
+        const int Gy = G / d;
+        const int rows = (g.ny + Gy - 1) / Gy, planes = (g.nz + d - 1) / d;
+        const int cost = ((rows + Rmax - 1) / Rmax) * (planes + (d > 1 ? 1 : 0) + 2);
+        if (best < 0 || cost < best) {
+          best = cost;
+          Gz = d;
+        }
+      }
+    }
+    const int Gy = G / Gz, ry = rank / Gz, rz = rank - ry * Gz;
+    jb0 = (int)((long long)ry * g.ny / Gy);
+    jb1 = (int)((long long)(ry + 1) * g.ny / Gy);
+    kb0 = (DIM == 3) ? (int)((long long)rz * g.nz / Gz) : 0;
+    kb1 = (DIM == 3) ? (int)((long long)(rz + 1) * g.nz / Gz) : 1;
   }
 
   // ---- staged pass on grid 0 ----------------------------------------------
@@ -313,7 +354,9 @@ struct Team {
 
   // ---- z-marching pass (3D) -------------------------------------------------
   // The owned rows of grid l are cut into y-tiles of Ry rows over the whole x
-  // extent, and each tile marches through the planes k = 0 .. nz-1.  LDS holds
+  // extent, and each tile marches through the owned planes [kb0, kb1), with
+  // one step on the layer below kb0 first (its top-face contributions) when
+  // kb0 > 0.  LDS holds
   // a ring of three planes of f0, f1 over the tile's rows plus a one-row halo,
   // four partial sums per element of one element layer, and per-thread areas:
   // the top-face contributions of the thread's elements of the previous layer,
@@ -336,17 +379,18 @@ struct Team {
   __device__ __forceinline__ void zmarch(int l, const T* __restrict__ f0, const T* __restrict__ f1,
                                          const T* __restrict__ f2, const T* __restrict__ f3, KV kval, MV mval,
                                          Body body) const {
-    constexpr int CE = 4;  // elements of a layer per thread
-    constexpr int CN = 5;  // staged nodes of a plane per thread
-    constexpr int CB = 4;  // output nodes of a plane per thread
+    constexpr int CE = kCE;  // elements of a layer per thread
+    constexpr int CN = kCN;  // staged nodes of a plane per thread
+    constexpr int CB = kCB;  // output nodes of a plane per thread
     const GridDev& g = L->g[l];
     const int nx = g.nx, ny = g.ny, nz = g.nz, EX = g.ex, EY = g.ey, EZ = g.ez;
     const unsigned mnx = g.mnx, mex = g.mex;
     const int plane = ny * nx, eplane = EY * EX;
     // tile rows: the LDS budget (set on the host) and the per-thread counts
     const int jb0 = l == 0 ? this->jb0 : 0, jb1 = l == 0 ? this->jb1 : ny;
-    const int Rmax = max(1, min((int)L->tile_y[l][sizeof(T) == 8 ? 0 : 1][0],
-                                min(CE * BLOCK / EX - 1, min(CN * BLOCK / nx - 2, CB * BLOCK / nx))));
+    const int kb0 = l == 0 ? this->kb0 : 0, kb1 = l == 0 ? this->kb1 : nz;
+    const int ks = max(kb0 - 1, 0);  // first step: the layer below the first owned plane
+    const int Rmax = zrows_max(l, sizeof(T));
     // as few tiles as Rmax allows, of equal height
     const int ntl = (jb1 - jb0 + Rmax - 1) / Rmax;
     const int Ry = (jb1 - jb0 + ntl - 1) / max(ntl, 1);
@@ -377,30 +421,38 @@ struct Team {
       // [elay] conductivities (per thread), 8-byte aligned after Q
       double* __restrict__ SG = reinterpret_cast<double*>(
           smem + (((size_t)(6 * lay + 8 * elay + 2 * nc) * sizeof(T) + 7) & ~(size_t)7));
-      // prologue: planes 0 and 1, conductivities of layer 0
-      for (int q = tid; q < lay; q += BLOCK) {
-        P[q] = g0[gn0 + q];
-        P[lay + q] = g1[gn0 + q];
-        P[2 * lay + q] = g0[plane + gn0 + q];
-        P[3 * lay + q] = g1[plane + gn0 + q];
+      // prologue: planes ks and ks + 1, conductivities of layer ks, and f2,
+      // f3 on plane kb0 when the march starts there
+      {
+        const size_t p0 = (size_t)ks * plane + gn0;
+        for (int q = tid; q < lay; q += BLOCK) {
+          P[q] = g0[p0 + q];
+          P[lay + q] = g1[p0 + q];
+          P[2 * lay + q] = g0[p0 + plane + q];
+          P[3 * lay + q] = g1[p0 + plane + q];
+        }
       }
       for (int q = tid; q < elay; q += BLOCK) {
-        SG[q] = sg[ge0 + q];
+        SG[q] = sg[(size_t)ks * eplane + ge0 + q];
 #pragma unroll
         for (int v = 0; v < 4; ++v) TP[v * elay + q] = T(0);
       }
-      for (int q = tid; q < nc; q += BLOCK) {
-        Q[q] = f2 ? g2[go0 + q] : T(0);
-        Q[nc + q] = f3 ? g3[go0 + q] : T(0);
+      if (ks == kb0) {
+        for (int q = tid; q < nc; q += BLOCK) {
+          Q[q] = f2 ? g2[(size_t)kb0 * plane + go0 + q] : T(0);
+          Q[nc + q] = f3 ? g3[(size_t)kb0 * plane + go0 + q] : T(0);
+        }
       }
       __syncthreads();
       int s0 = 0;  // ring slot of plane k
-      for (int k = 0; k < nz; ++k) {
+      for (int k = ks; k < kb1; ++k) {
         const int s1 = s0 == 2 ? 0 : s0 + 1;
         const int s2 = s1 == 2 ? 0 : s1 + 1;
         STM_T0(t_za);
         // ---- loads for later use ----
-        const bool pf = k + 2 < nz, ps = k + 1 < EZ, pq = k + 1 < nz;
+        // plane k+2 and layer k+1 when layer k+1 is computed (it adds to
+        // plane k+1 < kb1); f2, f3 of the next owned plane
+        const bool pf = k + 2 <= min(kb1, nz - 1), ps = k + 1 < min(kb1, EZ), pq = k + 1 < kb1;
         T r0[CN], r1[CN];
         if (pf) {
           const STM_GLOBAL T* __restrict__ g0p = g0 + (size_t)(k + 2) * plane + gn0;
@@ -485,9 +537,9 @@ struct Team {
         STM_T1P(t_za, 6);
         STM_T0(t_zb);
         __syncthreads();
-        // ---- phase B: output nodes of plane k ----
+        // ---- phase B: output nodes of plane k (an owned plane) ----
 #pragma unroll 1
-        for (int q = tid; q < nc; q += BLOCK) {
+        for (int q = tid; q < (k >= kb0 ? nc : 0); q += BLOCK) {
           const int r = fdiv(q, mnx);
           const int i = q - r * nx;
           const int j = j0 + r;
@@ -1430,8 +1482,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
   tm.ph = ph_acc;
 #endif
   const GridDev g0 = L->g[0];
-  tm.jb0 = (int)((long long)task.rank * g0.ny / task.G);
-  tm.jb1 = (int)((long long)(task.rank + 1) * g0.ny / task.G);
+  tm.set_box();
   const int n0 = g0.n;
   const int nb = tm.nband();
   double* __restrict__ u = reinterpret_cast<double*>(task.work + L->off_u);
@@ -1925,8 +1976,7 @@ __global__ __launch_bounds__(BLOCK) void st_global_kernel(const LevelDev* __rest
   tm.ph = ph_acc;
 #endif
   const GridDev g0 = L->g[0];
-  tm.jb0 = (int)((long long)task.rank * g0.ny / task.G);
-  tm.jb1 = (int)((long long)(task.rank + 1) * g0.ny / task.G);
+  tm.set_box();
   const int n0 = g0.n;
   const int nb = tm.nband();
   double* __restrict__ tact = reinterpret_cast<double*>(task.work + L->off_tact);
