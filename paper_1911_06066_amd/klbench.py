@@ -35,9 +35,14 @@ def main():
     modes = torch.from_numpy(klmodes.workload_modes(wl)[a.level]).to(dev)
     M = wl["n_modes"]
     xi = torch.from_numpy(stinputs.xi(wl["name"], a.level, a.samples, M)).to(dev)
-    ctx = Context(wl, precision=prec)
+    with Context(wl, precision=prec) as ctx:
+        run(ctx, a, modes, xi, M, prec)
+
+
+def run(ctx, a, modes, xi, M, prec):
+    import torch
     E = modes.shape[0]
-    out = torch.empty((a.samples, E), dtype=torch.float64, device=dev)
+    out = torch.empty((a.samples, E), dtype=torch.float64, device=modes.device)
     ctx.kl_synthesize(a.level, modes, xi, out=out)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
