@@ -17,7 +17,8 @@
 // map is updated as each slab is accepted.
 //
 // Teams: with G = 1 a workgroup owns the sample.  With G > 1 (levels without
-// coarse V-cycle grids) member r owns node rows [r ny / G, (r+1) ny / G) of the grid;
+// coarse V-cycle grids) member r owns a box of the grid (Team::set_box): a band
+// of node rows, in 3D of one group of planes;
 // passes end with a team barrier (agent-scope release/acquire around an
 // atomic counter, bounded wait) and reductions sum the members' partials in
 // rank order, so every member takes identical control-flow decisions.  Such
