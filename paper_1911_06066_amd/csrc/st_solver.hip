@@ -276,7 +276,7 @@ struct Team {
   // Rows per tile of a z-marching pass on grid l with fields of fbytes bytes:
   // the LDS budget (set on the host) and the per-thread element, staged-node
   // and output-node counts.
-  static constexpr int kCE = 4, kCN = 5, kCB = 4;
+  static constexpr int kCE = 3, kCN = 4, kCB = 3;
   __device__ __forceinline__ int zrows_max(int l, int fbytes) const {
     const GridDev& g = L->g[l];
     return max(1, min((int)L->tile_y[l][fbytes == 8 ? 0 : 1][0],

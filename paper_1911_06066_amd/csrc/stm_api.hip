@@ -184,10 +184,10 @@ stm_status validate_problem(stm_ctx* c, const stm_problem& p) {
         return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": team_seconds must be finite and >= 0");
     if ((int64_t)L.nx * L.ny * nz > (int64_t)1 << 28)
       return fail(c, STM_E_INVALID, "level " + std::to_string(l) + ": grid too large");
-    // a 3D pass gives each thread at most five staged node columns of a tile
-    // row (one row plus two halo rows at 256 threads per workgroup)
-    if (p.dim == 3 && L.nx > 400)
-      return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": 3D rows are limited to 400 nodes");
+    // a 3D pass gives each thread at most four staged node columns of a tile
+    // (one row plus two halo rows at 256 threads per workgroup)
+    if (p.dim == 3 && L.nx > 340)
+      return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": 3D rows are limited to 340 nodes");
     if ((int64_t)L.nx * L.ny * nz * std::max(L.nx, L.ny) >= (int64_t)1 << 32)
       return fail(c, STM_E_UNSUPPORTED, "level " + std::to_string(l) + ": grid too large for 32-bit index arithmetic");
     if (l > 0) {
