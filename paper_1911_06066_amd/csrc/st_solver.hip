@@ -357,32 +357,28 @@ struct Team {
   // The owned rows of grid l are cut into y-tiles of Ry rows over the whole x
   // extent, and each tile marches through the owned planes [kb0, kb1), with
   // one step on the layer below kb0 first (its top-face contributions) when
-  // kb0 > 0.  LDS holds
-  // a ring of three planes of f0, f1 over the tile's rows plus a one-row halo,
-  // four partial sums per element of one element layer, and per-thread areas:
-  // the top-face contributions of the thread's elements of the previous layer,
-  // their conductivities and f2, f3 at the thread's output nodes.  Element q of
-  // a layer and output node q of a plane always belong to thread q % BLOCK, so
-  // those areas need no barrier.  Step k:
-  //   * issue the loads of plane k+2 of f0, f1, of the conductivities of
-  //     element layer k+1 and of f2, f3 on plane k+1 (into registers);
+  // kb0 > 0.  LDS holds a ring of three planes of f0, f1 over the tile's rows
+  // plus a one-row halo, four partial sums per element of one element layer,
+  // two slots of the layer conductivities and of f2, f3 on the output rows,
+  // and per thread the top-face contributions of its elements of the previous
+  // layer (element q always belongs to thread q % BLOCK).  Step k:
+  //   * direct-to-LDS loads (no registers) of plane k+2 of f0, f1 into the
+  //     free ring slot, of the conductivities of layer k+1 and of f2, f3 on
+  //     plane k+1 into the other slots;
   //   * phase A: the vertex contributions of the thread's elements of layer k
   //     (between planes k and k+1) by sum factorisation; bottom-face ones plus
   //     the stored top-face ones of layer k-1 are the four sums the element
   //     gives plane k (to LDS); the new top-face ones replace the stored ones;
+  //   * an LDS-only barrier (the loads stay in flight);
   //   * phase B: every output node of plane k adds the sums of the four
   //     elements around it in its plane and calls body;
-  //   * the loaded values go to LDS (their latency overlapped both phases).
+  //   * a workgroup barrier, which also waits for the step's loads.
   // f0 and f1 are read from memory once per tile (plus the halo rows), f2, f3
-  // and the conductivities once; two workgroup barriers per plane.  Ends with
-  // a team barrier.
+  // and the conductivities once.  Ends with a team barrier.
   template <typename T, typename KV, typename MV, typename Body>
   __device__ __forceinline__ void zmarch(int l, const T* __restrict__ f0, const T* __restrict__ f1,
                                          const T* __restrict__ f2, const T* __restrict__ f3, KV kval, MV mval,
                                          Body body) const {
-    constexpr int CE = kCE;  // elements of a layer per thread
-    constexpr int CN = kCN;  // staged nodes of a plane per thread
-    constexpr int CB = kCB;  // output nodes of a plane per thread
     const GridDev& g = L->g[l];
     const int nx = g.nx, ny = g.ny, nz = g.nz, EX = g.ex, EY = g.ey, EZ = g.ez;
     const unsigned mnx = g.mnx, mex = g.mex;
@@ -406,6 +402,7 @@ struct Team {
     const T cxx = hy * hz / (T(36) * hx), cyy = hx * hz / (T(36) * hy), czz = hx * hy / (T(36) * hz);
     const T cxy = hz / T(24), cm = hx * hy * hz / T(216);
     const int tid = threadIdx.x;
+    constexpr int WT = sizeof(T) / 4;  // dwords per value
     T* __restrict__ P = reinterpret_cast<T*>(smem);
     for (int j0 = jb0; j0 < jb1; j0 += Ry) {
       const int je = min(j0 + Ry, jb1);          // output rows [j0, je)
@@ -418,73 +415,54 @@ struct Team {
       const int gn0 = jr0 * nx, ge0 = jr0 * EX, go0 = j0 * nx;
       T* __restrict__ S = P + 6 * lay;           // [4][elay] sums for plane k
       T* __restrict__ TP = S + 4 * elay;         // [4][elay] top-face contributions (per thread)
-      T* __restrict__ Q = TP + 4 * elay;         // [2][nc] f2, f3 on plane k (per thread)
-      // [elay] conductivities (per thread), 8-byte aligned after Q
+      T* __restrict__ Q = TP + 4 * elay;         // [2 slots][2][nc] f2, f3 on plane k
+      // [2 slots][elay] conductivities, 8-byte aligned after Q
       double* __restrict__ SG = reinterpret_cast<double*>(
-          smem + (((size_t)(6 * lay + 8 * elay + 2 * nc) * sizeof(T) + 7) & ~(size_t)7));
+          smem + (((size_t)(6 * lay + 8 * elay + 4 * nc) * sizeof(T) + 7) & ~(size_t)7));
+      // loads of plane kp of f0, f1 into ring slot sl, of layer kl's
+      // conductivities and of f2, f3 on plane kq into slot parity
+      auto load_plane = [&](int kp, int sl) {
+        const size_t base = (size_t)kp * plane + gn0;
+        dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g0 + base), P + (2 * sl) * lay, WT * lay);
+        dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g1 + base), P + (2 * sl + 1) * lay, WT * lay);
+      };
+      auto load_sigma = [&](int kl) {
+        dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(sg + (size_t)kl * eplane + ge0), SG + (kl & 1) * elay,
+                   2 * elay);
+      };
+      auto load_q = [&](int kq) {
+        T* qs = Q + (kq & 1) * 2 * nc;
+        if (f2) dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g2 + (size_t)kq * plane + go0), qs, WT * nc);
+        if (f3) dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g3 + (size_t)kq * plane + go0), qs + nc, WT * nc);
+      };
       // prologue: planes ks and ks + 1, conductivities of layer ks, and f2,
       // f3 on plane kb0 when the march starts there
-      {
-        const size_t p0 = (size_t)ks * plane + gn0;
-        for (int q = tid; q < lay; q += BLOCK) {
-          P[q] = g0[p0 + q];
-          P[lay + q] = g1[p0 + q];
-          P[2 * lay + q] = g0[p0 + plane + q];
-          P[3 * lay + q] = g1[p0 + plane + q];
-        }
-      }
       for (int q = tid; q < elay; q += BLOCK) {
-        SG[q] = sg[(size_t)ks * eplane + ge0 + q];
 #pragma unroll
         for (int v = 0; v < 4; ++v) TP[v * elay + q] = T(0);
       }
-      if (ks == kb0) {
-        for (int q = tid; q < nc; q += BLOCK) {
-          Q[q] = f2 ? g2[(size_t)kb0 * plane + go0 + q] : T(0);
-          Q[nc + q] = f3 ? g3[(size_t)kb0 * plane + go0 + q] : T(0);
-        }
-      }
+      if (!f2 || !f3)
+        for (int q = tid; q < 4 * nc; q += BLOCK) Q[q] = T(0);
+      __syncthreads();
+      load_plane(ks, 0);
+      load_plane(ks + 1, 1);
+      load_sigma(ks);
+      if (ks == kb0) load_q(kb0);
       __syncthreads();
       int s0 = 0;  // ring slot of plane k
       for (int k = ks; k < kb1; ++k) {
         const int s1 = s0 == 2 ? 0 : s0 + 1;
         const int s2 = s1 == 2 ? 0 : s1 + 1;
         STM_T0(t_za);
-        // ---- loads for later use ----
-        // plane k+2 and layer k+1 when layer k+1 is computed (it adds to
-        // plane k+1 < kb1); f2, f3 of the next owned plane
-        const bool pf = k + 2 <= min(kb1, nz - 1), ps = k + 1 < min(kb1, EZ), pq = k + 1 < kb1;
-        T r0[CN], r1[CN];
-        if (pf) {
-          const STM_GLOBAL T* __restrict__ g0p = g0 + (size_t)(k + 2) * plane + gn0;
-          const STM_GLOBAL T* __restrict__ g1p = g1 + (size_t)(k + 2) * plane + gn0;
-#pragma unroll
-          for (int c = 0; c < CN; ++c) {
-            const int q = tid + c * BLOCK;
-            if (q < lay) {
-              r0[c] = g0p[q];
-              r1[c] = g1p[q];
-            }
-          }
-        }
-        double rs[CE];
-        if (ps) {
-          const STM_GLOBAL double* __restrict__ gsp = sg + (size_t)(k + 1) * eplane + ge0;
-#pragma unroll
-          for (int c = 0; c < CE; ++c) {
-            const int q = tid + c * BLOCK;
-            if (q < elay) rs[c] = gsp[q];
-          }
-        }
-        T r2[CB], r3[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int q = tid + c * BLOCK;
-          r2[c] = (f2 && pq && q < nc) ? g2[(size_t)(k + 1) * plane + go0 + q] : T(0);
-          r3[c] = (f3 && pq && q < nc) ? g3[(size_t)(k + 1) * plane + go0 + q] : T(0);
-        }
+        // ---- loads for the next step: plane k+2 and layer k+1 when layer
+        // k+1 is computed (it adds to plane k+1 < kb1); f2, f3 of the next
+        // owned plane ----
+        if (k + 2 <= min(kb1, nz - 1)) load_plane(k + 2, s2);
+        if (k + 1 < min(kb1, EZ)) load_sigma(k + 1);
+        if (k + 1 < kb1) load_q(k + 1);
         const T* __restrict__ a0 = P + (2 * s0) * lay;
         const T* __restrict__ a1 = P + (2 * s0 + 1) * lay;
+        const double* __restrict__ sgk = SG + (k & 1) * elay;
         // ---- phase A: element layer k ----
         if (k < EZ) {
           const T* __restrict__ b0 = P + (2 * s1) * lay;
@@ -510,7 +488,7 @@ struct Team {
               x0[v] = (v & 4) ? b0[off] : a0[off];
               x1[v] = (v & 4) ? b1[off] : a1[off];
             }
-            const double se = SG[q];
+            const double se = sgk[q];
 #pragma unroll
             for (int v = 0; v < 4; ++v) tp[v] = TP[v * elay + q];
             __builtin_amdgcn_sched_barrier(0);
@@ -537,8 +515,9 @@ struct Team {
         }
         STM_T1P(t_za, 6);
         STM_T0(t_zb);
-        __syncthreads();
+        lds_barrier();
         // ---- phase B: output nodes of plane k (an owned plane) ----
+        const T* __restrict__ qk = Q + (k & 1) * 2 * nc;
 #pragma unroll 1
         for (int q = tid; q < (k >= kb0 ? nc : 0); q += BLOCK) {
           const int r = fdiv(q, mnx);
@@ -560,50 +539,38 @@ struct Team {
             }
           }
           const int o = (j - jr0) * nx + i;
-          const T o0 = a0[o], o1 = a1[o], o2 = Q[q], o3 = Q[nc + q];
+          const T o0 = a0[o], o1 = a1[o], o2 = qk[q], o3 = qk[nc + q];
           __builtin_amdgcn_sched_barrier(0);
           T y = T(0);
 #pragma unroll
           for (int e = 0; e < 4; ++e) y += ok[e] ? cv[e] : T(0);
           body(k * plane + go0 + q, i, j, k, y, o0, o1, o2, o3);
         }
-        // ---- loaded values to LDS (their latency overlapped both phases):
-        // plane k+2 into the free ring slot, the conductivities of layer k+1
-        // and f2, f3 on plane k+1 into this thread's own entries ----
-        if (pf) {
-          T* __restrict__ d0 = P + (2 * s2) * lay;
-          T* __restrict__ d1 = P + (2 * s2 + 1) * lay;
-#pragma unroll
-          for (int c = 0; c < CN; ++c) {
-            const int q = tid + c * BLOCK;
-            if (q < lay) {
-              d0[q] = r0[c];
-              d1[q] = r1[c];
-            }
-          }
-        }
-        if (ps) {
-#pragma unroll
-          for (int c = 0; c < CE; ++c) {
-            const int q = tid + c * BLOCK;
-            if (q < elay) SG[q] = rs[c];
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-          const int q = tid + c * BLOCK;
-          if (pq && q < nc) {
-            Q[q] = r2[c];
-            Q[nc + q] = r3[c];
-          }
-        }
-        __syncthreads();
+        __syncthreads();  // also waits for the step's direct-to-LDS loads
         STM_T1P(t_zb, 7);
         s0 = s1;
       }
     }
     if (G > 1) team_barrier();
   }
+
+  // n dwords from global memory to LDS by direct-to-LDS loads: lane i of the
+  // wave whose first thread is w writes dword w + i + c BLOCK of the range
+  // (the LDS address of a wave's load is uniform; lanes past n do not load).
+  // Complete after the next workgroup barrier that follows a fence.
+  __device__ __forceinline__ void dma_dwords(const STM_GLOBAL unsigned* __restrict__ src, void* dst, int n) const {
+    const int tid = threadIdx.x;
+    unsigned* d = reinterpret_cast<unsigned*>(dst);
+    const int wbase = tid & ~(kWave - 1);
+    for (int c0 = 0; c0 < n; c0 += BLOCK) {
+      if (c0 + tid < n)
+        __builtin_amdgcn_global_load_lds(src + c0 + tid, (__attribute__((address_space(3))) void*)(d + c0 + wbase), 4,
+                                         0, 0);
+    }
+  }
+  // Workgroup barrier ordering LDS accesses only: direct-to-LDS loads in
+  // flight stay in flight (a fence would wait for them).
+  __device__ __forceinline__ void lds_barrier() const { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
   // ---- tiled pass (2D) --------------------------------------------------------
   template <typename T, typename KV, typename MV, typename Body>
