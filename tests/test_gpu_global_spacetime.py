@@ -63,6 +63,7 @@ def _solve_global(torch, dev, wl, sig, **over):
     dict(dim=2, shape=(17, 17), m=16, precision="mixed", G=1, lanes=1, S=2),
     dict(dim=3, shape=(9, 9, 5), m=6, precision="fp64", G=1, lanes=0, S=2),
     dict(dim=3, shape=(17, 9, 5), m=6, precision="mixed", G=3, lanes=0, S=2),
+    dict(dim=3, shape=(9, 9, 17), m=4, precision="fp64", G=3, lanes=0, S=2),  # members by planes
 ])
 def test_global_solve_matches_oracle_monolithic(torch_dev, case):
     torch, dev = torch_dev

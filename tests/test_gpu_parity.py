@@ -278,6 +278,26 @@ def test_st_solve_3d_fp64_matches_oracle(torch_dev):
     assert np.abs(t.cpu().numpy() - t_ref).max() <= 1e-9 * wl["T"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plane_group_teams_match_oracle(torch_dev, precision):
+    """A team of 3 on 9 x 9 x 17 nodes splits its members by planes (three
+    groups of 5-6 planes over all 9 rows, each pass starting with a step on
+    the layer below the group): members read their neighbours' halo planes,
+    and every z-march starts away from plane 0 (rot3d fibre rows per layer)."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("slab3d", levels=[(9, 9, 17)], steps=[6], n_modes=8, kl_grid=(9, 9, 3),
+                           precision=precision, ic_radius=0.3, sigma_f0=4e-3)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    with Context(wl, team_size=3) as ctx:
+        u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+        assert all(s["status"] == 0 for s in stats), stats
+        assert ctx.timings()["solve_blocks"] == 3 * ctx.timings()["solve_teams"]
+        U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+        assert _rel(u.cpu().numpy(), U_ref) < (1e-9 if precision == "fp64" else 1e-8)
+
+
 @pytest.mark.parametrize("shape,precision,G", [((9, 9, 9), "fp64", 1), ((9, 9, 9), "mixed", 3),
                                                ((17, 17, 9), "fp64", 1), ((17, 17, 9), "fp64", 3),
                                                ((17, 17, 9), "mixed", 1), ((17, 17, 9), "mixed", 3)])
