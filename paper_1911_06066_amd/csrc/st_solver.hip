@@ -84,6 +84,24 @@ __device__ __forceinline__ const STM_CONST T* cmem(const T* p) {
   return (const STM_CONST T*)p;
 }
 
+// The stiffness argument c * v of a pass (kval(v, .) = c v).  The 3D pass
+// folds c into the element's conductivity factors instead of scaling the
+// eight vertex values; for c a power of two (the theta of backward Euler and
+// Crank-Nicolson, 1 - theta) both give the same floating-point result.
+template <typename T>
+struct KScale {
+  T c;
+  __device__ __forceinline__ T operator()(T a, T) const { return c * a; }
+};
+template <typename F>
+struct IsKScale {
+  static constexpr bool value = false;
+};
+template <typename T>
+struct IsKScale<KScale<T>> {
+  static constexpr bool value = true;
+};
+
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
 constexpr double kMinStep = 1.0 / 64;  // smallest damped fraction of a Newton step
 constexpr unsigned kSpinLimit = 1u << 25;
@@ -357,11 +375,13 @@ struct Team {
   // The owned rows of grid l are cut into y-tiles of Ry rows over the whole x
   // extent, and each tile marches through the owned planes [kb0, kb1), with
   // one step on the layer below kb0 first (its top-face contributions) when
-  // kb0 > 0.  LDS holds a ring of three planes of f0, f1 over the tile's rows
-  // plus a one-row halo, four partial sums per element of one element layer,
-  // two slots of the layer conductivities and of f2, f3 on the output rows,
-  // and per thread the top-face contributions of its elements of the previous
-  // layer (element q always belongs to thread q % BLOCK).  Step k:
+  // kb0 > 0.  LDS holds per thread the top-face contributions of its elements
+  // of the previous layer (element q always belongs to thread q % BLOCK; four
+  // values per element, read and written as one vector), a ring of three
+  // planes of f0, f1 over the tile's rows plus a one-row halo, four partial
+  // sums per element of one element layer with a border of zeros (one element
+  // each side in x and y), and two slots of f2, f3 on the output rows and of
+  // the layer conductivities.  Step k:
   //   * direct-to-LDS loads (no registers) of plane k+2 of f0, f1 into the
   //     free ring slot, of the conductivities of layer k+1 and of f2, f3 on
   //     plane k+1 into the other slots;
@@ -371,18 +391,22 @@ struct Team {
   //     gives plane k (to LDS); the new top-face ones replace the stored ones;
   //   * an LDS-only barrier (the loads stay in flight);
   //   * phase B: every output node of plane k adds the sums of the four
-  //     elements around it in its plane and calls body;
+  //     elements around it in its plane (the zero border stands for elements
+  //     outside the grid) and calls body;
   //   * a workgroup barrier, which also waits for the step's loads.
   // f0 and f1 are read from memory once per tile (plus the halo rows), f2, f3
-  // and the conductivities once.  Ends with a team barrier.
+  // and the conductivities once.  A stiffness argument kval = KScale{c} is
+  // folded into the element factors.  Ends with a team barrier.
   template <typename T, typename KV, typename MV, typename Body>
   __device__ __forceinline__ void zmarch(int l, const T* __restrict__ f0, const T* __restrict__ f1,
                                          const T* __restrict__ f2, const T* __restrict__ f3, KV kval, MV mval,
                                          Body body) const {
+    using T4 = T __attribute__((ext_vector_type(4)));
     const GridDev& g = L->g[l];
     const int nx = g.nx, ny = g.ny, nz = g.nz, EX = g.ex, EY = g.ey, EZ = g.ez;
     const unsigned mnx = g.mnx, mex = g.mex;
     const int plane = ny * nx, eplane = EY * EX;
+    const int EXP = EX + 2;  // padded element row
     // tile rows: the LDS budget (set on the host) and the per-thread counts
     const int jb0 = l == 0 ? this->jb0 : 0, jb1 = l == 0 ? this->jb1 : ny;
     const int kb0 = l == 0 ? this->kb0 : 0, kb1 = l == 0 ? this->kb1 : nz;
@@ -399,11 +423,14 @@ struct Team {
     const STM_GLOBAL T* __restrict__ g3 = gmem(f3);
     const double tau = prm.tau, zr = prm.zr;
     const T hx = T(g.hx), hy = T(g.hy), hz = T(g.hz);
-    const T cxx = hy * hz / (T(36) * hx), cyy = hx * hz / (T(36) * hy), czz = hx * hy / (T(36) * hz);
-    const T cxy = hz / T(24), cm = hx * hy * hz / T(216);
+    // the stiffness scale of a KScale argument goes into the element factors
+    T ksc = T(1);
+    if constexpr (IsKScale<KV>::value) ksc = kval.c;
+    const T cxx = ksc * (hy * hz / (T(36) * hx)), cyy = ksc * (hx * hz / (T(36) * hy));
+    const T czz = ksc * (hx * hy / (T(36) * hz)), cxy = ksc * (hz / T(24));
+    const T cm = hx * hy * hz / T(216);
     const int tid = threadIdx.x;
     constexpr int WT = sizeof(T) / 4;  // dwords per value
-    T* __restrict__ P = reinterpret_cast<T*>(smem);
     for (int j0 = jb0; j0 < jb1; j0 += Ry) {
       const int je = min(j0 + Ry, jb1);          // output rows [j0, je)
       const int jr0 = max(j0 - 1, 0);            // staged node rows [jr0, jr1]; element rows start there too
@@ -411,14 +438,16 @@ struct Team {
       const int ey1 = min(je - 1, EY - 1);       // element rows [jr0, ey1]
       const int lay = (jr1 - jr0 + 1) * nx;      // staged nodes per plane
       const int elay = (ey1 - jr0 + 1) * EX;     // elements per layer
+      const int slay = (ey1 - jr0 + 3) * EXP;    // padded sums per vertex slot
       const int nc = (je - j0) * nx;             // output nodes per plane
       const int gn0 = jr0 * nx, ge0 = jr0 * EX, go0 = j0 * nx;
-      T* __restrict__ S = P + 6 * lay;           // [4][elay] sums for plane k
-      T* __restrict__ TP = S + 4 * elay;         // [4][elay] top-face contributions (per thread)
-      T* __restrict__ Q = TP + 4 * elay;         // [2 slots][2][nc] f2, f3 on plane k
+      T4* __restrict__ TP = reinterpret_cast<T4*>(smem);  // [elay] top-face contributions (per thread)
+      T* __restrict__ P = reinterpret_cast<T*>(TP + elay);  // [3 slots][2][lay] f0, f1
+      T* __restrict__ S = P + 6 * lay;                      // [4][slay] sums for plane k
+      T* __restrict__ Q = S + 4 * slay;                     // [2 slots][2][nc] f2, f3 on plane k
       // [2 slots][elay] conductivities, 8-byte aligned after Q
       double* __restrict__ SG = reinterpret_cast<double*>(
-          smem + (((size_t)(6 * lay + 8 * elay + 4 * nc) * sizeof(T) + 7) & ~(size_t)7));
+          smem + (((size_t)elay * sizeof(T4) + (size_t)(6 * lay + 4 * slay + 4 * nc) * sizeof(T) + 7) & ~(size_t)7));
       // loads of plane kp of f0, f1 into ring slot sl, of layer kl's
       // conductivities and of f2, f3 on plane kq into slot parity
       auto load_plane = [&](int kp, int sl) {
@@ -435,12 +464,11 @@ struct Team {
         if (f2) dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g2 + (size_t)kq * plane + go0), qs, WT * nc);
         if (f3) dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(g3 + (size_t)kq * plane + go0), qs + nc, WT * nc);
       };
-      // prologue: planes ks and ks + 1, conductivities of layer ks, and f2,
-      // f3 on plane kb0 when the march starts there
-      for (int q = tid; q < elay; q += BLOCK) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) TP[v * elay + q] = T(0);
-      }
+      // prologue: zero top-face contributions and sums (the border stays
+      // zero), planes ks and ks + 1, conductivities of layer ks, and f2, f3
+      // on plane kb0 when the march starts there
+      for (int q = tid; q < elay; q += BLOCK) TP[q] = T4{T(0), T(0), T(0), T(0)};
+      for (int q = tid; q < 4 * slay; q += BLOCK) S[q] = T(0);
       if (!f2 || !f3)
         for (int q = tid; q < 4 * nc; q += BLOCK) Q[q] = T(0);
       __syncthreads();
@@ -480,8 +508,10 @@ struct Team {
           // waits), so one LDS round trip per element
 #pragma unroll 1
           for (int q = tid; q < elay; q += BLOCK) {
-            const int o = q + (int)fdiv(q, mex);  // staged node of the element's vertex (0, 0)
-            T x0[8], x1[8], tp[4];
+            const int r = (int)fdiv(q, mex);
+            const int o = q + r;                // staged node of the element's vertex (0, 0)
+            const int qp = o + r + EXP + 1;     // its padded sum slot
+            T x0[8], x1[8];
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
               const int off = o + (v & 1) + ((v >> 1) & 1) * nx;
@@ -489,28 +519,35 @@ struct Team {
               x1[v] = (v & 4) ? b1[off] : a1[off];
             }
             const double se = sgk[q];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) tp[v] = TP[v * elay + q];
+            const T4 tp = TP[q];
             __builtin_amdgcn_sched_barrier(0);
             T kv[8], mv[8], out[8];
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
-              kv[v] = kval(x0[v], x1[v]);
+              if constexpr (IsKScale<KV>::value)
+                kv[v] = x0[v];
+              else
+                kv[v] = kval(x0[v], x1[v]);
               mv[v] = mval(x0[v], x1[v]);
             }
             const T sT = T(se);
             elem_apply_3d<T>(kv, mv, sT * kx1 + kx0, sT * ky1 + ky0, sT * kz1 + kz0, (sT - tauT) * kxy, cm, out);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              S[v * elay + q] = tp[v] + out[v];
-              TP[v * elay + q] = out[v + 4];
-            }
+            S[qp] = tp.x + out[0];
+            S[slay + qp] = tp.y + out[1];
+            S[2 * slay + qp] = tp.z + out[2];
+            S[3 * slay + qp] = tp.w + out[3];
+            TP[q] = T4{out[4], out[5], out[6], out[7]};
           }
         } else {
 #pragma unroll 1
           for (int q = tid; q < elay; q += BLOCK) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) S[v * elay + q] = TP[v * elay + q];
+            const int r = (int)fdiv(q, mex);
+            const int qp = q + 2 * r + EXP + 1;
+            const T4 tp = TP[q];
+            S[qp] = tp.x;
+            S[slay + qp] = tp.y;
+            S[2 * slay + qp] = tp.z;
+            S[3 * slay + qp] = tp.w;
           }
         }
         STM_T1P(t_za, 6);
@@ -523,27 +560,18 @@ struct Team {
           const int r = fdiv(q, mnx);
           const int i = q - r * nx;
           const int j = j0 + r;
-          T cv[4];
-          bool ok[4];
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const int ey = j - 1 + b;
-            const bool oky = ey >= 0 && ey < EY;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-              const int ex = i - 1 + a;
-              ok[2 * b + a] = oky && ex >= 0 && ex < EX;
-              const int el = (ey - jr0) * EX + ex;
-              const int v = (1 - a) + 2 * (1 - b);
-              cv[2 * b + a] = S[v * elay + (ok[2 * b + a] ? el : 0)];
-            }
-          }
+          // element (i - 1 + a, j - 1 + b) gives vertex (1 - a) + 2 (1 - b)
+          const int e = (j - jr0) * EXP + i;
+          const T c0 = S[3 * slay + e], c1 = S[2 * slay + e + 1];
+          const T c2 = S[slay + e + EXP], c3 = S[e + EXP + 1];
           const int o = (j - jr0) * nx + i;
           const T o0 = a0[o], o1 = a1[o], o2 = qk[q], o3 = qk[nc + q];
           __builtin_amdgcn_sched_barrier(0);
           T y = T(0);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) y += ok[e] ? cv[e] : T(0);
+          y += c0;
+          y += c1;
+          y += c2;
+          y += c3;
           body(k * plane + go0 + q, i, j, k, y, o0, o1, o2, o3);
         }
         __syncthreads();  // also waits for the step's direct-to-LDS loads
@@ -905,7 +933,7 @@ struct Team {
       return;
     }
     staged<TI>(
-        l, x, w, b, di, [th = TI(prm.theta)](TI a, TI) { return th * a; }, [](TI a, TI ww) { return ww * a; },
+        l, x, w, b, di, KScale<TI>{TI(prm.theta)}, [](TI a, TI ww) { return ww * a; },
         [&](int idx, int, int, int, TI y, TI xo, TI, TI bo, TI dio) { gmem(out)[idx] = xo + om * (bo - y) * dio; });
   }
 
@@ -1217,7 +1245,7 @@ struct Team {
     bytes = uni(bytes + (4.0 * sizeof(TI) * n + dbytes(l)));
     const TI* __restrict__ w = mgW(l);
     staged<TI>(
-        l, x, w, b, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+        l, x, w, b, (const TI*)nullptr, KScale<TI>{TI(prm.theta)},
         [](TI a, TI ww) { return ww * a; }, [&](int idx, int, int, int, TI y, TI, TI, TI bo, TI) { gmem(out)[idx] = bo - y; });
   }
 
@@ -1375,7 +1403,7 @@ struct Team {
     for (int it = 0; it < prm.power_iters; ++it) {
       double nn[2] = {0.0, 0.0};
       staged<TI>(
-          l, x0, w, di, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+          l, x0, w, di, (const TI*)nullptr, KScale<TI>{TI(prm.theta)},
           [](TI a, TI ww) { return ww * a; },
           [&](int idx, int, int, int, TI ax, TI xown, TI, TI dio, TI) {
             const TI y = ax * dio;
@@ -1621,7 +1649,7 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           // pass A: ws = A Z_j (into V_{j+1})
           tm.bytes = uni(tm.bytes + (3.0 * sizeof(TI) * n0 + tm.dbytes(0)));
           tm.template staged<TI>(
-              0, Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, [th = TI(prm.theta)](TI a, TI) { return th * a; },
+              0, Zj, tm.mgW(0), (const TI*)nullptr, (const TI*)nullptr, KScale<TI>{TI(prm.theta)},
               [](TI a, TI ww) { return ww * a; },
               [&](int idx, int, int, int, TI w, TI, TI, TI, TI) { gmem(Vn)[idx] = w; });
           STM_T1(t_pa, 2);
@@ -2003,7 +2031,7 @@ __global__ __launch_bounds__(BLOCK) void st_global_kernel(const LevelDev* __rest
         if (k > 0) {
           tm.template staged<TI>(
               0, z + (k - 1) * vs, r + k * vs, (const TI*)nullptr, (const TI*)nullptr,
-              [c1 = TI(1.0 - th)](TI a, TI) { return c1 * a; }, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
+              KScale<TI>{TI(1.0 - th)}, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
               [&](int idx, int, int, int, TI y, TI, TI ro, TI, TI) { gmem(gT)[idx] = ro - y; });
           b = gT;
         }
@@ -2016,13 +2044,13 @@ __global__ __launch_bounds__(BLOCK) void st_global_kernel(const LevelDev* __rest
         TI* yk = y + k * vs;
         tm.template staged<TI>(
             0, x + k * vs, gW + k * vs, (const TI*)nullptr, (const TI*)nullptr,
-            [c1 = TI(th)](TI a, TI) { return c1 * a; }, [](TI a, TI ww) { return ww * a; },
+            KScale<TI>{TI(th)}, [](TI a, TI ww) { return ww * a; },
             [&](int idx, int, int, int, TI v, TI, TI, TI, TI) { gmem(yk)[idx] = v; });
         if (k > 0)
           // in place: f1 = y_k enters only the body (its own node), never the element terms
           tm.template staged<TI>(
               0, x + (k - 1) * vs, yk, (const TI*)nullptr, (const TI*)nullptr,
-              [c1 = TI(1.0 - th)](TI a, TI) { return c1 * a; }, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
+              KScale<TI>{TI(1.0 - th)}, [c0 = TI(-inv_dt)](TI a, TI) { return c0 * a; },
               [&](int idx, int, int, int, TI v, TI, TI yo, TI, TI) { gmem(yk)[idx] = yo + v; });
       }
     };

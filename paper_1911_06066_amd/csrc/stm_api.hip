@@ -353,19 +353,23 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
   // per field size and number of staged nodal fields (2 to 4)
   const size_t budget = (size_t)c->stage_bytes;
   for (int k = 0; k < nmg && p.dim == 3; ++k) {
-    // 3D passes march through the planes: a ring of three planes of two nodal
-    // fields over the tile's rows plus a one-row halo, four partial sums and
-    // four top-face contributions per element of one layer, two slots of two
-    // nodal fields over the tile's rows and of the layer's conductivities
-    // (float64).  The tallest tile within the budget (the kernel lowers it
-    // further to its per-thread counts).
+    // 3D passes march through the planes: four top-face contributions per
+    // element of one layer, a ring of three planes of two nodal fields over
+    // the tile's rows plus a one-row halo, four partial sums per element of
+    // one layer with a one-element border, two slots of two nodal fields over
+    // the tile's rows and of the layer's conductivities (float64).  The
+    // tallest tile within the budget (the kernel lowers it further to its
+    // per-thread counts).
     const GridDev& gk = d.g[k];
     for (int es = 0; es < 2; ++es) {
       const size_t fb = es == 0 ? 8 : 4;
       int by = 0;
       for (int ry = 1; ry <= gk.ny; ++ry) {
         const size_t sy = std::min(ry + 2, gk.ny), sey = std::min(ry + 1, gk.ey);
-        if (fb * (6 * sy * gk.nx + 8 * sey * gk.ex + 4 * (size_t)ry * gk.nx) + 16 * sey * gk.ex + 8 > budget) break;
+        const size_t bytes = fb * (4 * sey * gk.ex + 6 * sy * gk.nx + 4 * (sey + 2) * (gk.ex + 2) +
+                                   4 * (size_t)ry * gk.nx) +
+                             16 * sey * gk.ex + 8;
+        if (bytes > budget) break;
         by = ry;
       }
       if (by == 0) return fail(c, STM_E_UNSUPPORTED, "grid row too wide for the LDS staging budget");
