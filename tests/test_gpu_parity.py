@@ -279,6 +279,27 @@ def test_st_solve_3d_fp64_matches_oracle(torch_dev):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_theta_not_a_power_of_two_3d_matches_oracle(torch_dev, precision):
+    """theta = 0.75: the 3D passes fold the stiffness scale (theta, 1 - theta)
+    into the element factors instead of scaling the vertex values, which is
+    exact only for powers of two; any other theta must still give the
+    theta-scheme's discrete solution (a team of 3 by planes, rot3d fibres)."""
+    torch, dev = torch_dev
+    from paper_1911_06066_amd import Context
+    wl = stinputs.workload("slab3d", levels=[(9, 9, 17)], steps=[6], n_modes=8, kl_grid=(9, 9, 3),
+                           precision=precision, ic_radius=0.3, sigma_f0=4e-3, theta=0.75)
+    modes, xi = _inputs(wl, 2)
+    sig = oapi.kl_synthesize(modes[0], xi, wl["sigma_f0"])
+    with Context(wl, team_size=3) as ctx:
+        u, stats = ctx.st_solve(0, torch.from_numpy(sig).to(dev))
+        assert all(s["status"] == 0 for s in stats), stats
+    U_ref, _ = oapi.st_solve(wl, 0, sig, mode="timestep")
+    assert _rel(u.cpu().numpy(), U_ref) < (1e-9 if precision == "fp64" else 1e-8)
+    U_be, _ = oapi.st_solve(dict(wl, theta=1.0), 0, sig, mode="timestep")
+    assert _rel(U_be, U_ref) > 1e-6  # theta matters at this size
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_plane_group_teams_match_oracle(torch_dev, precision):
     """A team of 3 on 9 x 9 x 17 nodes splits its members by planes (three
     groups of 5-6 planes over all 9 rows, each pass starting with a step on
