@@ -102,6 +102,16 @@ struct IsKScale<KScale<T>> {
   static constexpr bool value = true;
 };
 
+// Storage type of the element conductivities a 3D pass in T reads.
+template <typename T>
+struct SigmaOf {
+  using type = double;
+};
+template <>
+struct SigmaOf<float> {
+  using type = float;
+};
+
 constexpr int kPartStride = 16;       // doubles per member in the partials buffer
 constexpr double kMinStep = 1.0 / 64;  // smallest damped fraction of a Newton step
 constexpr unsigned kSpinLimit = 1u << 25;
@@ -219,6 +229,15 @@ struct Team {
   }
   __device__ __forceinline__ const double* mgS(int l) const {
     return l == 0 ? sigma : reinterpret_cast<const double*>(work + L->off_mgS[l]);
+  }
+  // conductivities of grid l in the precision of a 3D pass in T (float32:
+  // the copy made once per sample)
+  template <typename T>
+  __device__ __forceinline__ const typename SigmaOf<T>::type* mgST(int l) const {
+    if constexpr (sizeof(T) == 4)
+      return reinterpret_cast<const float*>(work + L->off_mgS32[l]);
+    else
+      return mgS(l);
   }
   __device__ __forceinline__ double* mgK(int l) const {
     return l == 0 ? kdiag0 : reinterpret_cast<double*>(work + L->off_mgK[l]);
@@ -415,7 +434,9 @@ struct Team {
     // as few tiles as Rmax allows, of equal height
     const int ntl = (jb1 - jb0 + Rmax - 1) / Rmax;
     const int Ry = (jb1 - jb0 + ntl - 1) / max(ntl, 1);
-    const STM_GLOBAL double* __restrict__ sg = gmem(mgS(l));
+    using TS = typename SigmaOf<T>::type;
+    constexpr int WS = sizeof(TS) / 4;  // dwords per conductivity
+    const STM_GLOBAL TS* __restrict__ sg = gmem(mgST<T>(l));
     const STM_CONST double* __restrict__ fib = cmem(L->fib[l]);
     const STM_GLOBAL T* __restrict__ g0 = gmem(f0);
     const STM_GLOBAL T* __restrict__ g1 = gmem(f1);
@@ -446,7 +467,7 @@ struct Team {
       T* __restrict__ S = P + 6 * lay;                      // [4][slay] sums for plane k
       T* __restrict__ Q = S + 4 * slay;                     // [2 slots][2][nc] f2, f3 on plane k
       // [2 slots][elay] conductivities, 8-byte aligned after Q
-      double* __restrict__ SG = reinterpret_cast<double*>(
+      TS* __restrict__ SG = reinterpret_cast<TS*>(
           smem + (((size_t)elay * sizeof(T4) + (size_t)(6 * lay + 4 * slay + 4 * nc) * sizeof(T) + 7) & ~(size_t)7));
       // loads of plane kp of f0, f1 into ring slot sl, of layer kl's
       // conductivities and of f2, f3 on plane kq into slot parity
@@ -457,7 +478,7 @@ struct Team {
       };
       auto load_sigma = [&](int kl) {
         dma_dwords(reinterpret_cast<const STM_GLOBAL unsigned*>(sg + (size_t)kl * eplane + ge0), SG + (kl & 1) * elay,
-                   2 * elay);
+                   WS * elay);
       };
       auto load_q = [&](int kq) {
         T* qs = Q + (kq & 1) * 2 * nc;
@@ -490,7 +511,7 @@ struct Team {
         if (k + 1 < kb1) load_q(k + 1);
         const T* __restrict__ a0 = P + (2 * s0) * lay;
         const T* __restrict__ a1 = P + (2 * s0 + 1) * lay;
-        const double* __restrict__ sgk = SG + (k & 1) * elay;
+        const TS* __restrict__ sgk = SG + (k & 1) * elay;
         // ---- phase A: element layer k ----
         if (k < EZ) {
           const T* __restrict__ b0 = P + (2 * s1) * lay;
@@ -518,7 +539,7 @@ struct Team {
               x0[v] = (v & 4) ? b0[off] : a0[off];
               x1[v] = (v & 4) ? b1[off] : a1[off];
             }
-            const double se = sgk[q];
+            const TS se = sgk[q];
             const T4 tp = TP[q];
             __builtin_amdgcn_sched_barrier(0);
             T kv[8], mv[8], out[8];
@@ -826,6 +847,8 @@ struct Team {
               acc += Sf[(DIM == 2) ? (fy * gf.ex + fx) : ((fz * gf.ey + fy) * gf.ex + fx)];
             }
         Sc[e] = acc / (4 * cz);
+        if constexpr (DIM == 3 && sizeof(TI) == 4)
+          const_cast<float*>(mgST<TI>(l))[e] = float(Sc[e]);
       }
       __syncthreads();
       double* Kc = mgK(l);
@@ -862,6 +885,12 @@ struct Team {
           },
           0.0, &dd);
       kdiag0[idx] = dd;
+    }
+    if constexpr (DIM == 3 && sizeof(TI) == 4) {
+      // the members share the float32 conductivity copy of grid 0 out by
+      // element; the closing team barrier publishes it
+      float* s32 = const_cast<float*>(mgST<TI>(0));
+      for (int e = rank * BLOCK + tid; e < g0.ne; e += G * BLOCK) s32[e] = float(sigma[e]);
     }
     sync();
   }
@@ -1759,7 +1788,13 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
                 }
               }
             }
-            tm.template tsum<1>(nn);  // its barriers also publish V_{j+1}
+            // Only the last pass's norm is used.  A member reads V_{j+1} at
+            // its own nodes only, and in the same thread-to-node order as it
+            // wrote them, so the first pass ends with a workgroup barrier.
+            if (pass + 1 < kPasses)
+              __syncthreads();
+            else
+              tm.template tsum<1>(nn);
             STM_T1(t_pb, 4);
           }
           const double hn = uni(sqrt(nn[0]));

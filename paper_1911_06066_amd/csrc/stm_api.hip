@@ -324,6 +324,9 @@ stm_status build_level(stm_ctx* c, int l, LevelHost& out) {
       d.off_mgS[k] = take(8 * (size_t)g.ne);
       d.off_mgK[k] = take(8 * (size_t)g.n);
     }
+    // float32 copy of the conductivities, read by the float32 3D passes
+    // (the value each of them rounds to anyway)
+    if (c->inner_fp32 && p.dim == 3) d.off_mgS32[k] = take(4 * (size_t)g.ne);
   }
   // words per grid-0 node of one preconditioner application: smoothing sweeps
   // (5 words each) and, above the coarsest grid, the residual (5 words as a

@@ -58,6 +58,7 @@ struct LevelDev {
   int64_t off_mgI[kMaxMG];                              // inner [n_l] inverse slab diagonal (l >= 1)
   int64_t off_mgS[kMaxMG];                              // float64 [ne_l] conductivity: mean of children (l >= 1)
   int64_t off_mgK[kMaxMG];                              // float64 [n_l] stiffness diagonal (l >= 1)
+  int64_t off_mgS32[kMaxMG];                            // float32 [ne_l] conductivity for the float32 3D passes
   int64_t off_U;                                        // float64 [m][n0] in-place warm-start buffer
   // global space-time mode only (0 otherwise): inner space-time vectors of
   // m slabs of stride vs = n0 rounded up to 64
