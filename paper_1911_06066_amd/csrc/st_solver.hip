@@ -1688,16 +1688,19 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
           // column j of H.
           double nn[1] = {0.0};
           constexpr int kPasses = sizeof(TI) == 4 ? 2 : 1;
+          // dots of the next pass, accumulated by the first pass's update
+          double dnext[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          bool have_dots = false;
 #pragma unroll 1
           for (int pass = 0; pass < kPasses; ++pass) {
             STM_T0(t_dot);
             // dots with V_0..V_min(j,7) over the owned nodes: batched loads
             double d[9];
 #pragma unroll
-            for (int q = 0; q < 9; ++q) d[q] = 0.0;
+            for (int q = 0; q < 9; ++q) d[q] = have_dots ? dnext[q] : 0.0;
             const int nk0 = min(j + 1, 8);
-            tm.bytes = uni(tm.bytes + ((1.0 + nk0) * sizeof(TI) * n0));
-            {
+            if (!have_dots) {
+              tm.bytes = uni(tm.bytes + ((1.0 + nk0) * sizeof(TI) * n0));
               const TI* __restrict__ Vb = tm.V;
               const TI* __restrict__ Vr = Vn;
               for (int qb = tid; qb < nb; qb += BLOCK * 2) {
@@ -1755,42 +1758,85 @@ __global__ __launch_bounds__(BLOCK) void st_team_kernel(const LevelDev* __restri
             // pass B: V_{j+1} -= sum_q coef_q V_q over the owned nodes; norm
             nn[0] = 0.0;
             tm.bytes = uni(tm.bytes + ((j + 3.0) * sizeof(TI) * n0));
-            // vectors in chunks of 4, all loads of a chunk issued before use
-            for (int qb = tid; qb < nb; qb += BLOCK * 2) {
-              double w[2];
-              int ix[2];
+            // The first of two passes with at most 8 basis vectors also forms
+            // the second pass's dots from the values it holds: the same nodes
+            // per thread, the same operations in the same order as the
+            // separate loops, one read of the vectors fewer.
+            const bool fuse = pass + 1 < kPasses && j < 8;
+            if (fuse) {
 #pragma unroll
-              for (int uu = 0; uu < 2; ++uu) {
-                const int q = qb + uu * BLOCK;
-                ix[uu] = q < nb ? tm.bidx(q) : 0;
-                w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
-              }
-              for (int q0 = 0; q0 <= j; q0 += 4) {
-                TI vv[4][2];
+              for (int q = 0; q < 9; ++q) dnext[q] = 0.0;
+              for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+                double w[2];
+                int ix[2];
+                TI vv[2][8];
 #pragma unroll
-                for (int p = 0; p < 4; ++p)
+                for (int uu = 0; uu < 2; ++uu) {
+                  const int q = qb + uu * BLOCK;
+                  ix[uu] = q < nb ? tm.bidx(q) : 0;
+                  w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
 #pragma unroll
-                  for (int uu = 0; uu < 2; ++uu)
-                    vv[p][uu] = (q0 + p <= j) ? tm.V[(q0 + p) * vs + ix[uu]] : TI(0);
-#pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                  const double cq = (q0 + p <= j) ? coef[q0 + p] : 0.0;
-#pragma unroll
-                  for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[p][uu]);
+                  for (int p = 0; p < 8; ++p) vv[uu][p] = (p <= j && q < nb) ? tm.V[p * vs + ix[uu]] : TI(0);
                 }
-              }
 #pragma unroll
-              for (int uu = 0; uu < 2; ++uu) {
-                if (qb + uu * BLOCK < nb) {
-                  const TI wt = TI(w[uu]);
-                  Vn[ix[uu]] = wt;
-                  nn[0] += double(wt) * double(wt);
+                for (int p = 0; p < 8; ++p) {
+                  const double cq = p <= j ? coef[p] : 0.0;
+#pragma unroll
+                  for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[uu][p]);
+                }
+                TI wt[2];
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu) {
+                  wt[uu] = TI(0);
+                  if (qb + uu * BLOCK < nb) {
+                    wt[uu] = TI(w[uu]);
+                    Vn[ix[uu]] = wt[uu];
+                  }
+                }
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu)
+#pragma unroll
+                  for (int p = 0; p < 8; ++p) dnext[p] += double(vv[uu][p]) * double(wt[uu]);
+              }
+            } else {
+              // vectors in chunks of 4, all loads of a chunk issued before use
+              for (int qb = tid; qb < nb; qb += BLOCK * 2) {
+                double w[2];
+                int ix[2];
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu) {
+                  const int q = qb + uu * BLOCK;
+                  ix[uu] = q < nb ? tm.bidx(q) : 0;
+                  w[uu] = q < nb ? double(Vn[ix[uu]]) : 0.0;
+                }
+                for (int q0 = 0; q0 <= j; q0 += 4) {
+                  TI vv[4][2];
+#pragma unroll
+                  for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int uu = 0; uu < 2; ++uu)
+                      vv[p][uu] = (q0 + p <= j) ? tm.V[(q0 + p) * vs + ix[uu]] : TI(0);
+#pragma unroll
+                  for (int p = 0; p < 4; ++p) {
+                    const double cq = (q0 + p <= j) ? coef[q0 + p] : 0.0;
+#pragma unroll
+                    for (int uu = 0; uu < 2; ++uu) w[uu] -= cq * double(vv[p][uu]);
+                  }
+                }
+#pragma unroll
+                for (int uu = 0; uu < 2; ++uu) {
+                  if (qb + uu * BLOCK < nb) {
+                    const TI wt = TI(w[uu]);
+                    Vn[ix[uu]] = wt;
+                    nn[0] += double(wt) * double(wt);
+                  }
                 }
               }
             }
             // Only the last pass's norm is used.  A member reads V_{j+1} at
             // its own nodes only, and in the same thread-to-node order as it
             // wrote them, so the first pass ends with a workgroup barrier.
+            have_dots = fuse;
             if (pass + 1 < kPasses)
               __syncthreads();
             else
